@@ -1,0 +1,21 @@
+"""Seeded synthetic workloads for structured-FISTA image restoration.
+
+This package only *makes inputs*: true images, point spread functions, the
+blurred and noisy observation, and the random start vector of the Lipschitz
+power iteration.  It holds none of the restoration method's arithmetic (no
+Kronecker approximation, no FISTA step).  Both the FP64 oracle and the GPU
+library consume exactly the arrays produced here.
+"""
+
+from .inputs import (  # noqa: F401
+    CONFIGS,
+    Problem,
+    add_noise,
+    blur,
+    config,
+    gaussian_psf,
+    make_image,
+    motion_psf,
+    power_start,
+    batch_problems,
+)
