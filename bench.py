@@ -1,0 +1,182 @@
+#!/usr/bin/env python3
+"""sFISTA benchmark on one MI355X.
+
+Workload: the 2048 x 2048 precision configuration (reflexive boundary,
+rotated Gaussian PSF sigma = (4, 12), theta = 30 deg, r = 5 Kronecker terms,
+1% noise, lambda = 0.02, 300 iterations, split-BF16x3 GEMMs with
+float-float iterate state).  One timed step is the whole path on one
+synthetic image already resident in HBM: the Kronecker approximation
+(kron_approx), the plan setup with the power iteration for L, 300
+iterations of Algorithm 2 and the FP64 report.  `value` is iterations per
+second of whole steps.
+
+Prints one JSON line on stdout; progress goes to stderr.
+"""
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "sFISTA iters/sec + MFMA TFLOP/s at 2048², r=5; rel err vs FP64 oracle"
+PEAK_TFLOPS = {"bf16x3": 2516.6, "bf16": 2516.6, "fp16": 2516.6, "fp32": 157.3, "fp64": 78.6}
+MFMA_PER_PRODUCT = {"bf16x3": 3, "bf16": 1, "fp16": 1, "fp32": 1, "fp64": 1}
+GEMM_NAMES = ["F1 T=Y*A^T", "F2 R=B*T-Bobs", "G1 S=B^T*R", "G2 sum S*A + update"]
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--n", type=int, default=2048, help="image size (the workload is 2048)")
+    ap.add_argument("--iters", type=int, default=300)
+    ap.add_argument("--precision", default="bf16x3", choices=sorted(PEAK_TFLOPS))
+    ap.add_argument("--power-iters", type=int, default=30)
+    ap.add_argument("--cpu-iters", type=int, default=3, help="oracle iterations timed for cpu_baseline")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-fp32-compare", action="store_true")
+    args = ap.parse_args()
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(the design for sharding is described in DESIGN.md).", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import synth as S
+    from paper_1901_00913_amd import sfista
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(2)
+    sfista.lib()
+    dev = torch.device("cuda:0")
+
+    log(f"[bench] generating the {args.n}x{args.n} workload")
+    p = S.config(3, n=args.n, iters=args.iters)
+    m, n = p.shape
+    l, q = p.center
+    r, lam, bc, iters = p.r, p.lam, p.bc, p.iters
+    P = torch.as_tensor(p.psf).to(dev)
+    Bobs = torch.as_tensor(p.bobs).to(dev)
+    v0 = torch.as_tensor(p.v0).to(dev)
+    torch.cuda.synchronize()
+
+    def step(timing):
+        A, B, sigma, eps = sfista.kron_approx(P, l, q, bc, r)
+        s = sfista.Solver(Bobs, A, B, lam=lam, precision=args.precision, power_iters=args.power_iters, v0=v0)
+        if timing:
+            s.set_timing(True)
+        _, rep = s.solve(iters, want_x=False)
+        kt = s.kernel_times() if timing else None
+        L = s.L
+        s.close()
+        return rep, kt, L, eps
+
+    for w in range(args.warmup):
+        log(f"[bench] warmup step {w + 1}/{args.warmup}")
+        step(False)
+    torch.cuda.synchronize()
+    reps, kts = [], []
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        rep, kt, L, eps = step(True)
+        reps.append(rep)
+        kts.append(kt)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    elapsed = t1 - t0
+    value = iters * args.steps / elapsed
+    log(f"[bench] {args.steps} steps in {elapsed:.3f} s -> {value:.1f} it/s")
+
+    # per-GEMM mean device times over the timed steps
+    avg = [0.0] * 4
+    cnt = [0] * 4
+    for ms, c in kts:
+        for g in range(4):
+            avg[g] += ms[g] * c[g]
+            cnt[g] += c[g]
+    avg = [a / c if c else 0.0 for a, c in zip(avg, cnt)]
+    flops = [2.0 * r * m * n * n, 2.0 * r * m * m * n, 2.0 * r * m * m * n, 2.0 * r * m * n * n]
+    dom = max(range(4), key=lambda g: avg[g] * cnt[g])
+    achieved = flops[dom] / (avg[dom] * 1e-3) / 1e12
+    peak = PEAK_TFLOPS[args.precision]
+    iter_s = float(np.mean([rp["seconds"] for rp in reps]))
+    iter_rate = iters / iter_s
+    alg_tflops_iter = 8.0 * r * n ** 3 / (iter_s / iters) / 1e12 if m == n else None
+
+    extra = {
+        "iteration_only_its": iter_rate,
+        "iteration_alg_tflops": alg_tflops_iter,
+        "setup_ms_per_step": elapsed / args.steps * 1e3 - iter_s * 1e3,
+        "gemm_avg_ms": dict(zip(GEMM_NAMES, avg)),
+        "gemm_alg_tflops": {GEMM_NAMES[g]: flops[g] / (avg[g] * 1e-3) / 1e12 for g in range(4) if avg[g] > 0},
+        "L": L, "eps_s": eps, "resid_rel": reps[-1]["resid_rel"], "phi_s": reps[-1]["phi_s"],
+    }
+
+    if not args.no_fp32_compare and args.precision != "fp32":
+        log("[bench] plain FP32 comparison solve")
+        A, B, _, _ = sfista.kron_approx(P, l, q, bc, r)
+        s = sfista.Solver(Bobs, A, B, lam=lam, L=L, precision="fp32", pair_state=False)
+        _, rep32 = s.solve(iters, want_x=False)
+        s.close()
+        extra["fp32_iteration_only_its"] = iters / rep32["seconds"]
+        extra["speedup_vs_fp32"] = rep32["seconds"] / iter_s
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        import oracle as O
+        try:
+            from threadpoolctl import threadpool_info
+            threads = max([t.get("num_threads", 1) for t in threadpool_info()] or [1])
+        except Exception:
+            threads = os.cpu_count()
+        log("[bench] cpu_baseline: oracle Kronecker setup (untimed)")
+        K, H, _, _, _, _ = O.kron_approx64(p.psf, l, q, bc, r)
+        Lfix = 1.02   # a fixed step constant shared by both sides of the rel-err check
+        log(f"[bench] cpu_baseline: timing {args.cpu_iters} oracle iterations")
+        c0 = time.perf_counter()
+        Xo = O.sfista64(K, H, p.bobs, lam, Lfix, args.cpu_iters)
+        c1 = time.perf_counter()
+        A, B, _, _ = sfista.kron_approx(P, l, q, bc, r)
+        s = sfista.Solver(Bobs, A, B, lam=lam, L=Lfix, precision=args.precision)
+        Xg, _ = s.solve(args.cpu_iters)
+        s.close()
+        rel_err = float(np.linalg.norm(Xg.cpu().numpy() - Xo) / np.linalg.norm(Xo))
+        cpu = {"value": args.cpu_iters / (c1 - c0), "unit": "iters/s", "cores": threads, "kind": "oracle",
+               "sample": f"{args.cpu_iters} FP64 numpy sFISTA iterations at {m}x{n}, r={r} "
+                         f"(Kronecker setup excluded)",
+               "rel_err_gpu_vs_oracle": rel_err, "rel_err_iters": args.cpu_iters}
+        log(f"[bench] cpu_baseline {cpu['value']:.3f} it/s on {threads} threads; rel err {rel_err:.3e}")
+
+    out = {
+        "metric": METRIC, "value": value, "unit": "iters/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": elapsed / args.steps * 1e3, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": args.precision, "data": "synthetic",
+        "config": {"workload": f"sfista-{m}x{n}-r{r}-reflexive-{iters}it", "image": [m, n], "rank": r,
+                   "iters": iters, "precision": args.precision, "lambda": lam,
+                   "power_iters": args.power_iters, "parallelism": "single-gpu"},
+        "roofline": {"bound": "mfma", "kernel": f"gemm_nt ({GEMM_NAMES[dom]})", "achieved": achieved,
+                     "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak, "traffic": None,
+                     "mfma_products_per_flop": MFMA_PER_PRODUCT[args.precision],
+                     "mfma_util": achieved * MFMA_PER_PRODUCT[args.precision] / peak},
+        "cpu_baseline": cpu,
+        "extra": extra,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

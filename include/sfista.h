@@ -1,0 +1,166 @@
+/*
+ * sfista.h -- C ABI of the MI355X (gfx950) structured-FISTA library.
+ *
+ * The library solves the Tikhonov-regularised image-restoration problem of
+ * Chen, Nagy, Xi and Yu, "Structured FISTA for Image Restoration", in its
+ * matrix form (Section 1, "matrix minimization model"):
+ *
+ *     min_X  1/2 || sum_k B_k X A_k^T - Bobs ||_F^2  +  lambda^2/2 ||X||_F^2
+ *
+ * where the blur matrix is approximated by a sum of r Kronecker products,
+ * A ~ A_s = sum_k A_k (x) B_k (Section 2; the paper writes K_i for the right
+ * factor A_k and H_i for the left factor B_k, and s for r).
+ *
+ * Conventions for every call:
+ *   - images, PSFs and factors are row-major: X[i*n + j], i the row (0..m-1);
+ *     the PSF has the same orientation as the image;
+ *   - A holds r right factors A_k (n x n) back to back, B holds r left factors
+ *     B_k (m x m) back to back, each row-major;
+ *   - pointers marked (device) are HIP device memory, (host) host memory;
+ *     the caller owns every buffer it passes; the library never frees them;
+ *   - calls return SFISTA_OK (0) or a negative sfista_status; no exception or
+ *     abort crosses the ABI; sfista_last_error() gives a message for the
+ *     calling thread's last failure;
+ *   - arguments are validated on the host before any device work starts.
+ */
+#ifndef SFISTA_H
+#define SFISTA_H
+
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    SFISTA_OK = 0,
+    SFISTA_ERR_ARG = -1,          /* invalid argument (null pointer, size, range) */
+    SFISTA_ERR_UNSUPPORTED = -2,  /* valid but not supported (unknown mode, size too large) */
+    SFISTA_ERR_NOMEM = -3,        /* device allocation failed */
+    SFISTA_ERR_HIP = -4,          /* a HIP runtime call failed */
+    SFISTA_ERR_NONFINITE = -5     /* a final norm or the Lipschitz estimate is not finite */
+} sfista_status;
+
+/* Boundary condition of the blur (Section 2).  The periodic boundary is
+ * excluded by the paper and not offered. */
+typedef enum { SFISTA_BC_ZERO = 0, SFISTA_BC_REFLEXIVE = 1 } sfista_bc;
+
+/* Arithmetic of the four GEMMs of one iteration.
+ *   FP64   : FP64 MFMA, FP64 iterate state.
+ *   FP32   : FP32 MFMA, FP32 accumulation.
+ *   BF16   : BF16 MFMA, FP32 accumulation (operands rounded to bf16).
+ *   FP16   : FP16 MFMA, FP32 accumulation (operands rounded to fp16).
+ *   BF16X3 : every operand split as hi + lo in bf16; the product is
+ *            a_hi b_hi + a_hi b_lo + a_lo b_hi on BF16 MFMA, FP32 accumulation.
+ * Non-FP64 modes keep the iterate state in FP32 or float-float (pair_state). */
+typedef enum {
+    SFISTA_FP64 = 0, SFISTA_FP32 = 1, SFISTA_BF16 = 2, SFISTA_FP16 = 3, SFISTA_BF16X3 = 4
+} sfista_precision;
+
+typedef struct {
+    double lambda;       /* Tikhonov parameter, finite and >= 0 (Section 1) */
+    double L;            /* Lipschitz constant of the data term, lambda_max(A_s^T A_s)
+                            (Algorithm 2's input); <= 0 asks the library to estimate it
+                            by power iteration */
+    int precision;       /* sfista_precision */
+    int nonneg;          /* 1: project every iterate on X >= 0 (the constraint of
+                            Section 1); 0: Algorithm 2 as printed */
+    int power_iters;     /* power-iteration steps when L <= 0; 0 selects 30 */
+    int pair_state;      /* non-FP64 modes: 1 keeps X in float-float (hi + lo fp32),
+                            0 in plain fp32; ignored in FP64 mode */
+    const double* x0;    /* (device) m x n initial point X_0, or NULL for X_0 = 0 */
+    const double* v0;    /* (device) m x n start of the power iteration, or NULL for a
+                            fixed internal start */
+} sfista_params;
+
+typedef struct {
+    int iters;           /* iterations completed by the plan so far */
+    double seconds;      /* device time of the iterations run by this solve call */
+    double L;            /* Lipschitz constant in use */
+    double phi_s;        /* 1/2||A_s x - b||^2 + lambda^2/2||x||^2 at the returned X (FP64 sums) */
+    double resid_norm;   /* ||sum_k B_k X A_k^T - Bobs||_F */
+    double bobs_norm;    /* ||Bobs||_F */
+    double x_norm;       /* ||X||_F */
+    double resid_rel;    /* resid_norm / bobs_norm (gamma of Section 4, for A_s) */
+    int status;          /* sfista_status of the solve */
+} sfista_report;
+
+typedef struct sfista_plan* sfista_handle;
+
+/* Kronecker approximation of the blur (Section 2, Theorem 1).
+ *   P      (device) m x n FP64 PSF, peak at the 0-based centre (l, q).
+ *   bc     sfista_bc.
+ *   r      number of Kronecker terms, 1 <= r <= min(m, n).
+ *   A      (device, out) r x n x n FP64 right factors (Toeplitz for the zero
+ *          boundary, Toeplitz + Hankel for the reflexive one).
+ *   B      (device, out) r x m x m FP64 left factors.
+ *   sigma  (host, out, nullable) the r largest singular values of the weighted
+ *          PSF P_bar of Theorem 1.
+ *   eps_s  (host, out, nullable) ||P_bar - sum_{k<=r} sigma_k u_k v_k^T||_F, which
+ *          equals ||A - A_s||_F by Theorem 1.
+ * The left factor B_k is built from the left singular vector u_k and the row
+ * centre l, the right factor A_k from v_k and the column centre q.  Signs are
+ * fixed so that the largest-magnitude entry of u_k is positive.  All device
+ * work is FP64 on `stream`; the call synchronises the stream before returning. */
+int kron_approx(const double* P, int m, int n, int l, int q, int bc, int r,
+                double* A, double* B, double* sigma, double* eps_s, hipStream_t stream);
+
+/* Build a solver plan for Algorithm 2 (sFISTA).
+ *   Bobs   (device) m x n FP64 observed image.
+ *   A, B   (device) dense factors as produced by kron_approx (any real factors
+ *          are accepted).
+ *   p      (host) parameters; p->L <= 0 runs the power iteration.
+ *   out    (host, out) the new handle.
+ * The plan allocates and owns its device buffers, packs the factors into the
+ * operand layouts of its GEMMs, sets X_0 and synchronises `stream`, so the
+ * caller may free its inputs afterwards.  All later work of the plan runs on
+ * `stream`. */
+int sfista_setup(const double* Bobs, int m, int n, const double* A, const double* B, int r,
+                 const sfista_params* p, hipStream_t stream, sfista_handle* out);
+
+/* Run `iters` more iterations of Algorithm 2 (Steps 1-3 each), asynchronously
+ * on the plan's stream, with no host synchronisation.  The iteration count
+ * and the momentum sequence t_k continue from the previous call, so
+ * step(a) followed by step(b) equals step(a + b). */
+int sfista_step(sfista_handle h, int iters);
+
+/* Run up to `max_iters` more iterations, then evaluate the final report.
+ * tol > 0 stops early once ||X_k - X_{k-1}||_F <= tol ||X_k||_F (checked every
+ * 10 iterations; the paper stops after a fixed count, tol = 0).
+ *   X_out (device, out, nullable) m x n FP64 copy of the current iterate.
+ *   rep   (host, out, nullable) report.
+ * Synchronous: returns after the stream has drained. */
+int sfista_solve(sfista_handle h, int max_iters, double tol, double* X_out, sfista_report* rep);
+
+/* Apply the approximate blur and its normal operator with the plan's GEMMs
+ * and precision (Section 1, "matrix equation"; Theorem 3's proof):
+ *   AX  (device, out, nullable) m x n FP64: sum_k B_k X A_k^T
+ *   AtAX(device, out, nullable) m x n FP64: sum_j B_j^T (sum_k B_k X A_k^T) A_j
+ * X (device) m x n FP64.  Does not touch the iterate state.  Synchronous. */
+int sfista_apply(sfista_handle h, const double* X, double* AX, double* AtAX);
+
+/* Per-kernel timing of the iteration's four GEMMs (F1: T_k = Y A_k^T,
+ * F2: R = sum_k B_k T_k - Bobs, G1: S_k = B_k^T R, G2: sum_k S_k A_k with the
+ * fused update).  While enabled, every GEMM launch of sfista_step /
+ * sfista_solve is bracketed by HIP events on the plan's stream.
+ * sfista_kernel_times synchronises the stream and returns, per GEMM
+ * (index 0..3 = F1, F2, G1, G2), the mean device time in milliseconds
+ * (avg_ms, host, 4 entries) and the number of timed launches (launches, host,
+ * 4 entries), then clears the accumulated samples. */
+int sfista_set_timing(sfista_handle h, int enable);
+int sfista_kernel_times(sfista_handle h, double* avg_ms, long* launches);
+
+/* Lipschitz constant in use by the plan (estimated or given). */
+int sfista_get_L(sfista_handle h, double* L);
+
+/* Release the plan and its device buffers (synchronises its stream). */
+void sfista_destroy(sfista_handle h);
+
+/* Message describing the calling thread's last failure ("" if none). */
+const char* sfista_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SFISTA_H */

@@ -52,23 +52,23 @@ BC_REFLEXIVE = 1
 
 def toep(c, j: int) -> np.ndarray:
     """Banded Toeplitz matrix whose ``j``-th column (1-based) equals ``c``
-    (Section 2, definition of ``toep(c, j)`` and its 5x5 example)."""
+    (Section 2, definition of ``toep(c, j)`` and its 5x5 example): column
+    ``col`` is ``c`` moved down by ``col - (j - 1)`` rows, zero-filled."""
     c = np.asarray(c, dtype=np.float64)
     n = c.shape[0]
-    t = np.zeros((n, n))
-    for col in range(n):
-        shift = col - (j - 1)          # column ``col`` is ``c`` moved down by ``shift``
-        for i in range(n):
-            src = i - shift
-            if 0 <= src < n:
-                t[i, col] = c[src]
-    return t
+    i = np.arange(n)[:, None]
+    col = np.arange(n)[None, :]
+    src = i - (col - (j - 1))
+    ok = (src >= 0) & (src < n)
+    return np.where(ok, c[np.clip(src, 0, n - 1)], 0.0)
 
 
 def hank(c, j: int) -> np.ndarray:
     """Banded Hankel matrix whose first row is ``[c_{j+1}, ..., c_n, 0, ..., 0]``
     and whose last column is ``[0, ..., 0, c_1, ..., c_{j-1}]^T`` (1-based
-    ``j``; Section 2, definition of ``hank(c, j)`` and its 5x5 example)."""
+    ``j``; Section 2, definition of ``hank(c, j)`` and its 5x5 example).  A
+    Hankel matrix is constant along anti-diagonals ``d = i + k``: the first
+    row gives ``d < n`` and the last column ``d >= n - 1``."""
     c = np.asarray(c, dtype=np.float64)
     n = c.shape[0]
     first_row = np.zeros(n)
@@ -78,12 +78,9 @@ def hank(c, j: int) -> np.ndarray:
     head = c[:max(0, j - 1)]           # c_1 .. c_{j-1}
     if head.shape[0]:
         last_col[n - head.shape[0]:] = head
-    h = np.empty((n, n))
-    for i in range(n):
-        for k in range(n):
-            d = i + k                   # a Hankel matrix is constant on anti-diagonals
-            h[i, k] = first_row[d] if d < n else last_col[d - n + 1]
-    return h
+    antidiag = np.concatenate([first_row, last_col[1:]])   # value on anti-diagonal d
+    d = np.arange(n)[:, None] + np.arange(n)[None, :]
+    return antidiag[d]
 
 
 def factor(c, center0: int, bc: int) -> np.ndarray:

@@ -1,0 +1,293 @@
+// Element-wise kernels, GEMM epilogues and deterministic reductions of the
+// sFISTA iteration (Algorithm 2).
+#pragma once
+
+#include "common.hpp"
+
+namespace sf {
+
+// ------------------------------------------------------------- reductions
+// Deterministic sum of squares: a fixed grid of RED_BLOCKS blocks writes one
+// partial each (fixed lane/tree order), then one block adds the partials in
+// index order.  No atomics, so results are bitwise reproducible.
+constexpr int RED_BLOCKS = 512;
+constexpr int RED_THREADS = 256;
+
+__device__ __forceinline__ double block_sum(double v, double* sh) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  if (lane == 0) sh[wave] = v;
+  __syncthreads();
+  double tot = 0.0;
+  if (threadIdx.x == 0) {
+    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) tot += sh[w];
+  }
+  __syncthreads();
+  return tot;   // valid in thread 0
+}
+
+// F(e) returns the value whose square is accumulated, for e in [0, count).
+template <class F>
+__global__ __launch_bounds__(RED_THREADS) void sumsq_partial_kernel(F f, long count, double* partial) {
+  __shared__ double sh[RED_THREADS / 64];
+  double acc = 0.0;
+  for (long e = blockIdx.x * (long)RED_THREADS + threadIdx.x; e < count; e += (long)RED_BLOCKS * RED_THREADS) {
+    const double v = f(e);
+    acc += v * v;
+  }
+  const double t = block_sum(acc, sh);
+  if (threadIdx.x == 0) partial[blockIdx.x] = t;
+}
+
+static __global__ __launch_bounds__(RED_THREADS) void sum_partials_kernel(const double* partial, int count, double* out) {
+  __shared__ double sh[RED_THREADS / 64];
+  double acc = 0.0;
+  for (int e = threadIdx.x; e < count; e += RED_THREADS) acc += partial[e];
+  const double t = block_sum(acc, sh);
+  if (threadIdx.x == 0) *out = t;
+}
+
+template <class F>
+hipError_t sumsq(F f, long count, double* partial, double* out, hipStream_t s) {
+  hipLaunchKernelGGL(sumsq_partial_kernel<F>, dim3(RED_BLOCKS), dim3(RED_THREADS), 0, s, f, count, partial);
+  hipLaunchKernelGGL(sum_partials_kernel, dim3(1), dim3(RED_THREADS), 0, s, partial, RED_BLOCKS, out);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------- state views
+// Iterate-state storage: FP64 mode keeps doubles; other modes keep either
+// float pairs (hi, lo) or plain floats.  Dense m x n, row-major.
+enum StateKind : int { ST_F64 = 0, ST_PAIR = 1, ST_F32 = 2 };
+
+__device__ __forceinline__ double state_get(const void* st, int kind, long e) {
+  if (kind == ST_F64) return static_cast<const double*>(st)[e];
+  if (kind == ST_PAIR) {
+    const float2 p = static_cast<const float2*>(st)[e];
+    return static_cast<double>(p.x) + static_cast<double>(p.y);
+  }
+  return static_cast<double>(static_cast<const float*>(st)[e]);
+}
+
+__device__ __forceinline__ void state_set(void* st, int kind, long e, double v) {
+  if (kind == ST_F64) {
+    static_cast<double*>(st)[e] = v;
+  } else if (kind == ST_PAIR) {
+    const float hi = static_cast<float>(v);
+    static_cast<float2*>(st)[e] = make_float2(hi, static_cast<float>(v - static_cast<double>(hi)));
+  } else {
+    static_cast<float*>(st)[e] = static_cast<float>(v);
+  }
+}
+
+struct StateSq {          // ||X||^2
+  const void* st; int kind;
+  __device__ double operator()(long e) const { return state_get(st, kind, e); }
+};
+struct StateDiffSq {      // ||X_a - X_b||^2
+  const void* a; const void* b; int kind;
+  __device__ double operator()(long e) const { return state_get(a, kind, e) - state_get(b, kind, e); }
+};
+struct DoubleSq {
+  const double* p;
+  __device__ double operator()(long e) const { return p[e]; }
+};
+
+// ------------------------------------------------------------- element-wise
+// X_0 -> both state buffers and the F1 operand planes of Y_1 = X_0.
+template <int MODE>
+__global__ void init_state_kernel(const double* x0, void* st0, void* st1, int kind,
+                                  void* y0, void* y1, long ldy, int m, int n) {
+  void* y[2] = {y0, y1};
+  const long total = (long)m * n;
+  for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < total; e += (long)gridDim.x * blockDim.x) {
+    const double v = x0 ? x0[e] : 0.0;
+    state_set(st0, kind, e, v);
+    state_set(st1, kind, e, v);
+    const long i = e / n, j = e - i * n;
+    store_planes<MODE>(y, i * ldy + j, v);
+  }
+}
+
+// Dense m x n doubles, optionally scaled by 1/sqrt(*sumsq), -> operand planes.
+template <int MODE>
+__global__ void to_planes_kernel(const double* x, const double* sumsq, void* p0, void* p1, long ldp,
+                                 int m, int n) {
+  void* p[2] = {p0, p1};
+  const double scale = sumsq ? 1.0 / sqrt(*sumsq) : 1.0;
+  const long total = (long)m * n;
+  for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < total; e += (long)gridDim.x * blockDim.x) {
+    const long i = e / n, j = e - i * n;
+    store_planes<MODE>(p, i * ldp + j, x[e] * scale);
+  }
+}
+
+// Iterate state -> operand planes (used to evaluate the residual at X_k).
+template <int MODE>
+__global__ void state_to_planes_kernel(const void* st, int kind, void* p0, void* p1, long ldp, int m, int n) {
+  void* p[2] = {p0, p1};
+  const long total = (long)m * n;
+  for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < total; e += (long)gridDim.x * blockDim.x) {
+    const long i = e / n, j = e - i * n;
+    if (kind == ST_PAIR) {
+      const float2 v = static_cast<const float2*>(st)[e];
+      store_planes<MODE>(p, i * ldp + j, static_cast<double>(v.x), v.y);
+    } else {
+      store_planes<MODE>(p, i * ldp + j, state_get(st, kind, e));
+    }
+  }
+}
+
+static __global__ void state_to_double_kernel(const void* st, int kind, double* out, long total) {
+  for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < total; e += (long)gridDim.x * blockDim.x)
+    out[e] = state_get(st, kind, e);
+}
+
+// Bobs (m x n, double) -> its transpose (n x m) in the accumulator type.
+template <class T>
+__global__ void transpose_to_kernel(const double* src, T* dst, int m, int n) {
+  __shared__ double tile[32][33];
+  const int bi = blockIdx.y * 32, bj = blockIdx.x * 32;
+  for (int r = threadIdx.y; r < 32; r += blockDim.y) {
+    const int i = bi + r, j = bj + threadIdx.x;
+    if (i < m && j < n) tile[r][threadIdx.x] = src[(long)i * n + j];
+  }
+  __syncthreads();
+  for (int r = threadIdx.y; r < 32; r += blockDim.y) {
+    const int j = bj + r, i = bi + threadIdx.x;
+    if (i < m && j < n) dst[(long)j * m + i] = static_cast<T>(tile[threadIdx.x][r]);
+  }
+}
+
+// Factor packing into the four operand layouts of the iteration's GEMMs.
+// d is the factor size (n for A_k, m for B_k); src holds r factors d x d.
+enum PackKind : int {
+  PK_STACK = 0,     // rows (k, a) of r*d, cols b:   F_k[a][b]     (F1's W = A stack)
+  PK_CAT = 1,       // rows a, cols (k, b):          F_k[a][b]     (F2's [B_1 ... B_r])
+  PK_STACK_T = 2,   // rows (k, a), cols b:          F_k[b][a]     (G1's [B_1^T; ...; B_r^T])
+  PK_CAT_T = 3      // rows a, cols (k, b):          F_k[b][a]     (G2's [A_1; ...; A_r]^T)
+};
+
+template <int MODE>
+__global__ void pack_kernel(const double* __restrict__ src, void* o0, void* o1, long ldo, int kind,
+                            int d, long rows, long cols) {
+  void* o[2] = {o0, o1};
+  const long total = rows * cols;
+  for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < total; e += (long)gridDim.x * blockDim.x) {
+    const long row = e / cols, col = e - row * cols;
+    long s;
+    if (kind == PK_STACK) {
+      s = row * d + col;
+    } else if (kind == PK_CAT) {
+      const long k = col / d, b = col - k * d;
+      s = (k * d + row) * d + b;
+    } else if (kind == PK_STACK_T) {
+      const long k = row / d, a = row - k * d;
+      s = (k * d + col) * d + a;
+    } else {
+      const long k = col / d, b = col - k * d;
+      s = (k * d + b) * d + row;
+    }
+    store_planes<MODE>(o, row * ldo + col, src[s]);
+  }
+}
+
+// ------------------------------------------------------------- epilogues
+// F1 / G1: output row p = (k, a) of a term-stacked GEMM goes to row a and
+// column block k of the next operand: out[a * ldo + k * colblk + col].
+template <int MODE>
+struct EpiStack {
+  void* out[2];
+  long ldo;
+  int D, colblk;
+  __device__ __forceinline__ void operator()(int row, int col, typename ModeTraits<MODE>::Acc v) const {
+    const int k = row / D;
+    const int a = row - k * D;
+    const long idx = (long)a * ldo + (long)k * colblk + col;
+    if constexpr (MODE == M_F64) store_planes<MODE>(out, idx, v);
+    else store_planes_f<MODE>(out, idx, v);
+  }
+};
+
+// F2: R^T[j][i] = (sum_k B_k T_k)^T[j][i] - Bobs^T[j][i] (Step 1's inner
+// residual); `copy` (optional) receives R[i][j] in FP64.
+template <int MODE>
+struct EpiResid {
+  using Acc = typename ModeTraits<MODE>::Acc;
+  void* out[2];
+  long ldo;
+  const Acc* bobs_t;   // n x m, nullable (normal-operator products only)
+  int m;
+  double* copy;        // m x n, nullable
+  int n;
+  __device__ __forceinline__ void operator()(int j, int i, Acc v) const {
+    const Acc r = bobs_t ? v - bobs_t[(long)j * m + i] : v;
+    const long idx = (long)j * ldo + i;
+    if constexpr (MODE == M_F64) store_planes<MODE>(out, idx, r);
+    else store_planes_f<MODE>(out, idx, r);
+    if (copy) copy[(long)i * n + j] = static_cast<double>(r);
+  }
+};
+
+// G2 without update: raw FP64 copy of the normal-operator product.
+template <int MODE>
+struct EpiStore {
+  double* out;
+  int n;
+  __device__ __forceinline__ void operator()(int i, int j, typename ModeTraits<MODE>::Acc v) const {
+    out[(long)i * n + j] = static_cast<double>(v);
+  }
+};
+
+// G2 + Steps 1 and 3 of Algorithm 2, fused:
+//   Y_k     = X_{k-1} + beta_{k-1} (X_{k-1} - X_{k-2})
+//   X_k     = (L Y_k - G) / (L + lambda^2)          [max(0, .) if nonneg]
+//   Y_{k+1} = X_k + beta_k (X_k - X_{k-1})
+// G is the accumulator sum_j B_j^T R A_j.  X_k overwrites X_{k-2} in place.
+// The planes of Y_{k+1} feed the next iteration's F1.
+template <int MODE, int KIND>
+struct EpiUpdate {
+  using Acc = typename ModeTraits<MODE>::Acc;
+  void* y[2];
+  long ldy;
+  const void* x1;   // X_{k-1}
+  void* x2;         // X_{k-2} in, X_k out
+  int n;
+  double c1, c2;    // L / (L + lambda^2), 1 / (L + lambda^2)
+  double bp, bc;    // beta_{k-1}, beta_k
+  int nonneg;
+  __device__ __forceinline__ void operator()(int i, int j, Acc g) const {
+    const long s = (long)i * n + j;
+    const long o = (long)i * ldy + j;
+    if constexpr (KIND == ST_F64) {
+      const double a1 = static_cast<const double*>(x1)[s];
+      const double a2 = static_cast<double*>(x2)[s];
+      const double yk = a1 + bp * (a1 - a2);
+      double xk = c1 * yk - c2 * static_cast<double>(g);
+      if (nonneg) xk = fmax(xk, 0.0);
+      const double yn = xk + bc * (xk - a1);
+      static_cast<double*>(x2)[s] = xk;
+      store_planes<MODE>(y, o, yn);
+    } else if constexpr (KIND == ST_PAIR) {
+      const float2 p1 = static_cast<const float2*>(x1)[s];
+      const float2 p2 = static_cast<float2*>(x2)[s];
+      const ff a1{p1.x, p1.y}, a2{p2.x, p2.y};
+      const ff yk = ff_add(a1, ff_mul(ff_from_double(bp), ff_add(a1, ff_neg(a2))));
+      ff xk = ff_add(ff_mul(ff_from_double(c1), yk), ff_neg(ff_mul_f(ff_from_double(c2), static_cast<float>(g))));
+      if (nonneg && (xk.hi < 0.f || (xk.hi == 0.f && xk.lo < 0.f))) xk = ff{0.f, 0.f};
+      const ff yn = ff_add(xk, ff_mul(ff_from_double(bc), ff_add(xk, ff_neg(a1))));
+      static_cast<float2*>(x2)[s] = make_float2(xk.hi, xk.lo);
+      store_planes_f<MODE>(y, o, yn.hi, yn.lo);
+    } else {
+      const float a1 = static_cast<const float*>(x1)[s];
+      const float a2 = static_cast<float*>(x2)[s];
+      const float yk = a1 + static_cast<float>(bp) * (a1 - a2);
+      float xk = static_cast<float>(c1) * yk - static_cast<float>(c2) * static_cast<float>(g);
+      if (nonneg) xk = fmaxf(xk, 0.f);
+      const float yn = xk + static_cast<float>(bc) * (xk - a1);
+      static_cast<float*>(x2)[s] = xk;
+      store_planes_f<MODE>(y, o, yn);
+    }
+  }
+};
+
+}  // namespace sf

@@ -1,0 +1,195 @@
+"""Python binding of libsfista.so (argument marshalling only).
+
+Every call forwards device pointers of torch tensors and the current HIP
+stream to the C ABI declared in ``include/sfista.h``; all arithmetic runs in
+the library's HIP kernels.  PyTorch only allocates device memory and provides
+the stream.  There is no fallback: if the shared library is missing or fails
+to load, every entry point raises.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libsfista.so")
+
+SFISTA_OK = 0
+SFISTA_ERR_ARG = -1
+SFISTA_ERR_UNSUPPORTED = -2
+SFISTA_ERR_NOMEM = -3
+SFISTA_ERR_HIP = -4
+SFISTA_ERR_NONFINITE = -5
+
+BC_ZERO = 0
+BC_REFLEXIVE = 1
+
+PRECISIONS = {"fp64": 0, "fp32": 1, "bf16": 2, "fp16": 3, "bf16x3": 4}
+
+EXPORTS = ("kron_approx", "sfista_setup", "sfista_step", "sfista_solve", "sfista_apply",
+           "sfista_set_timing", "sfista_kernel_times", "sfista_get_L", "sfista_destroy",
+           "sfista_last_error")
+
+
+class SfistaError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"sfista error {code}: {msg}")
+        self.code = code
+
+
+class Params(ctypes.Structure):
+    _fields_ = [("lambda_", ctypes.c_double), ("L", ctypes.c_double), ("precision", ctypes.c_int),
+                ("nonneg", ctypes.c_int), ("power_iters", ctypes.c_int), ("pair_state", ctypes.c_int),
+                ("x0", ctypes.c_void_p), ("v0", ctypes.c_void_p)]
+
+
+class Report(ctypes.Structure):
+    _fields_ = [("iters", ctypes.c_int), ("seconds", ctypes.c_double), ("L", ctypes.c_double),
+                ("phi_s", ctypes.c_double), ("resid_norm", ctypes.c_double),
+                ("bobs_norm", ctypes.c_double), ("x_norm", ctypes.c_double),
+                ("resid_rel", ctypes.c_double), ("status", ctypes.c_int)]
+
+    def as_dict(self):
+        return {name: getattr(self, name) for name, _ in self._fields_}
+
+
+_lib = None
+
+
+def lib() -> ctypes.CDLL:
+    """Load libsfista.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with `python -m paper_1901_00913_amd.build`")
+    L = ctypes.CDLL(LIB_PATH)
+    vp, i, d = ctypes.c_void_p, ctypes.c_int, ctypes.c_double
+    L.kron_approx.argtypes = [vp, i, i, i, i, i, i, vp, vp, vp, vp, vp]
+    L.sfista_setup.argtypes = [vp, i, i, vp, vp, i, ctypes.POINTER(Params), vp, ctypes.POINTER(vp)]
+    L.sfista_step.argtypes = [vp, i]
+    L.sfista_solve.argtypes = [vp, i, d, vp, ctypes.POINTER(Report)]
+    L.sfista_apply.argtypes = [vp, vp, vp, vp]
+    L.sfista_get_L.argtypes = [vp, ctypes.POINTER(d)]
+    L.sfista_set_timing.argtypes = [vp, i]
+    L.sfista_kernel_times.argtypes = [vp, ctypes.POINTER(d), ctypes.POINTER(ctypes.c_long)]
+    L.sfista_destroy.argtypes = [vp]
+    L.sfista_destroy.restype = None
+    L.sfista_last_error.argtypes = []
+    L.sfista_last_error.restype = ctypes.c_char_p
+    for name in ("kron_approx", "sfista_setup", "sfista_step", "sfista_solve", "sfista_apply", "sfista_get_L",
+                 "sfista_set_timing", "sfista_kernel_times"):
+        getattr(L, name).restype = ctypes.c_int
+    _lib = L
+    return L
+
+
+def _check(rc: int):
+    if rc != SFISTA_OK:
+        raise SfistaError(rc, lib().sfista_last_error().decode())
+
+
+def _stream(stream=None) -> int:
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return s.cuda_stream
+
+
+def _dev_f64(t, name):
+    import torch
+    if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == torch.float64 and t.is_contiguous()):
+        raise TypeError(f"{name} must be a contiguous float64 CUDA tensor")
+    return t.data_ptr()
+
+
+def kron_approx(P, l: int, q: int, bc: int, r: int, stream=None):
+    """Kronecker approximation of the blur with PSF ``P`` (m x n, float64, on
+    the GPU): returns ``(A, B, sigma, eps_s)`` with ``A`` (r, n, n) right
+    factors, ``B`` (r, m, m) left factors (device tensors), ``sigma`` the r
+    leading singular values of the weighted PSF and ``eps_s = ||A - A_s||_F``."""
+    import torch
+    m, n = P.shape
+    A = torch.empty((r, n, n), dtype=torch.float64, device=P.device)
+    B = torch.empty((r, m, m), dtype=torch.float64, device=P.device)
+    sig = (ctypes.c_double * max(r, 1))()
+    eps = ctypes.c_double(0.0)
+    _check(lib().kron_approx(_dev_f64(P, "P"), m, n, l, q, bc, r, A.data_ptr(), B.data_ptr(),
+                             ctypes.cast(sig, ctypes.c_void_p), ctypes.cast(ctypes.byref(eps), ctypes.c_void_p),
+                             _stream(stream)))
+    return A, B, np.array(sig[:r]), eps.value
+
+
+class Solver:
+    """sFISTA plan (Algorithm 2) for one image."""
+
+    def __init__(self, Bobs, A, B, lam: float, L: Optional[float] = None, precision: str = "bf16x3",
+                 nonneg: bool = False, power_iters: int = 0, pair_state: bool = True, x0=None, v0=None,
+                 stream=None):
+        m, n = Bobs.shape
+        r = A.shape[0]
+        if A.shape != (r, n, n) or B.shape != (r, m, m):
+            raise ValueError("A must be (r, n, n) and B (r, m, m) for Bobs of shape (m, n)")
+        p = Params(float(lam), float(L) if L is not None else 0.0, PRECISIONS[precision], int(bool(nonneg)),
+                   int(power_iters), int(bool(pair_state)),
+                   _dev_f64(x0, "x0") if x0 is not None else None,
+                   _dev_f64(v0, "v0") if v0 is not None else None)
+        h = ctypes.c_void_p()
+        self._h = None
+        self.shape = (m, n)
+        self.device = Bobs.device
+        self._stream = stream
+        _check(lib().sfista_setup(_dev_f64(Bobs, "Bobs"), m, n, _dev_f64(A, "A"), _dev_f64(B, "B"), r,
+                                  ctypes.byref(p), _stream(stream), ctypes.byref(h)))
+        self._h = h
+
+    @property
+    def L(self) -> float:
+        v = ctypes.c_double()
+        _check(lib().sfista_get_L(self._h, ctypes.byref(v)))
+        return v.value
+
+    def step(self, iters: int):
+        _check(lib().sfista_step(self._h, int(iters)))
+
+    def solve(self, max_iters: int, tol: float = 0.0, want_x: bool = True):
+        import torch
+        X = torch.empty(self.shape, dtype=torch.float64, device=self.device) if want_x else None
+        rep = Report()
+        _check(lib().sfista_solve(self._h, int(max_iters), float(tol), X.data_ptr() if want_x else None,
+                                  ctypes.byref(rep)))
+        return X, rep.as_dict()
+
+    def apply(self, X, want_ax: bool = True, want_atax: bool = True):
+        """``(sum_k B_k X A_k^T, A_s^T A_s X)`` with the plan's GEMMs."""
+        import torch
+        ax = torch.empty(self.shape, dtype=torch.float64, device=self.device) if want_ax else None
+        atax = torch.empty(self.shape, dtype=torch.float64, device=self.device) if want_atax else None
+        _check(lib().sfista_apply(self._h, _dev_f64(X, "X"), ax.data_ptr() if want_ax else None,
+                                  atax.data_ptr() if want_atax else None))
+        return ax, atax
+
+    def set_timing(self, enable: bool = True):
+        _check(lib().sfista_set_timing(self._h, int(bool(enable))))
+
+    def kernel_times(self):
+        """Mean device milliseconds and launch counts of the four GEMMs
+        (F1, F2, G1, G2) timed since the last call."""
+        ms = (ctypes.c_double * 4)()
+        cnt = (ctypes.c_long * 4)()
+        _check(lib().sfista_kernel_times(self._h, ms, cnt))
+        return list(ms), list(cnt)
+
+    def close(self):
+        if self._h is not None:
+            lib().sfista_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,91 @@
+"""C-ABI checks that need no GPU: the library loads, exports every function
+declared in include/sfista.h, and rejects invalid arguments before any
+device work."""
+
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared_functions():
+    src = open(os.path.join(ROOT, "include", "sfista.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    names = re.findall(r"^\s*(?:int|void|const char\*)\s+(\w+)\s*\(", src, flags=re.M)
+    return sorted(set(names))
+
+
+def test_header_declares_the_boundary():
+    names = _declared_functions()
+    for required in ("kron_approx", "sfista_setup", "sfista_step", "sfista_solve"):
+        assert required in names
+
+
+def test_library_exports_every_declared_symbol():
+    from paper_1901_00913_amd import sfista
+    lib = sfista.lib()
+    for name in _declared_functions():
+        assert hasattr(lib, name), name
+    assert set(_declared_functions()) == set(sfista.EXPORTS)
+
+
+@pytest.fixture(scope="module")
+def L():
+    from paper_1901_00913_amd import sfista
+    return sfista.lib()
+
+
+def _params(**kw):
+    from paper_1901_00913_amd.sfista import Params
+    p = Params(0.1, 1.0, 4, 0, 0, 1, None, None)
+    for k, v in kw.items():
+        setattr(p, k, v)
+    return p
+
+
+FAKE = ctypes.c_void_p(0x1000)   # never dereferenced: validation fails first
+
+
+@pytest.mark.parametrize("case,expect", [
+    (dict(m=0), -1), (dict(n=-3), -1), (dict(r=0), -1), (dict(r=5, m=4, n=4), -1),
+    (dict(lambda_=-1.0), -1), (dict(lambda_=float("nan")), -1), (dict(L=float("inf")), -1),
+    (dict(precision=7), -2), (dict(power_iters=-1), -1),
+])
+def test_setup_rejects_invalid_arguments(L, case, expect):
+    m, n, r = case.pop("m", 4), case.pop("n", 4), case.pop("r", 1)
+    p = _params(**case)
+    h = ctypes.c_void_p()
+    rc = L.sfista_setup(FAKE, m, n, FAKE, FAKE, r, ctypes.byref(p), None, ctypes.byref(h))
+    assert rc == expect
+    assert h.value is None
+    assert L.sfista_last_error()
+
+
+def test_setup_rejects_null_pointers(L):
+    h = ctypes.c_void_p()
+    p = _params()
+    assert L.sfista_setup(None, 4, 4, FAKE, FAKE, 1, ctypes.byref(p), None, ctypes.byref(h)) == -1
+    assert L.sfista_setup(FAKE, 4, 4, FAKE, FAKE, 1, None, None, ctypes.byref(h)) == -1
+    assert L.sfista_setup(FAKE, 4, 4, FAKE, FAKE, 1, ctypes.byref(p), None, None) == -1
+
+
+@pytest.mark.parametrize("args,expect", [
+    ((4, 4, 4, 1, 0, 1), -1),    # l out of range
+    ((4, 4, 1, -1, 0, 1), -1),   # q out of range
+    ((4, 4, 1, 1, 2, 1), -1),    # unknown boundary
+    ((4, 4, 1, 1, 0, 5), -1),    # r > min(m, n)
+    ((64, 64, 1, 1, 0, 40), -2), # r beyond the supported subspace width
+])
+def test_kron_approx_rejects_invalid_arguments(L, args, expect):
+    m, n, l, q, bc, r = args
+    assert L.kron_approx(FAKE, m, n, l, q, bc, r, FAKE, FAKE, None, None, None) == expect
+
+
+def test_handle_calls_reject_null(L):
+    assert L.sfista_step(None, 1) == -1
+    assert L.sfista_solve(None, 1, 0.0, None, None) == -1
+    assert L.sfista_apply(None, FAKE, None, None) == -1
+    L.sfista_destroy(None)
