@@ -23,7 +23,9 @@
 // Lane l feeds row/column (l % 16) and the chunk (l / 16) of the segment for
 // both operands, so the k-index assignment is identical on both sides and
 // the hardware's internal k order is immaterial.  The accumulator of a 16x16
-// block holds, in lane l, column (l % 16) and rows 4*(l/16) + t, t = 0..3.
+// block holds, in lane l, column (l % 16) and four rows: 4*(l/16) + t for
+// the f32-accumulating instructions, (l/16) + 4*t for the f64 one
+// (t = 0..3, the accumulator register).
 #pragma once
 
 #include "common.hpp"
@@ -217,7 +219,8 @@ void gemm_nt_kernel(GemmArgs g, Epi epi) {
   }
 
   // epilogue
-  const int row0 = tm * BM + wm * WM + (lane >> 4) * 4;
+  constexpr int RSTEP = (MODE == M_F64) ? 4 : 1;          // row stride between accumulator registers
+  const int row0 = tm * BM + wm * WM + (lane >> 4) * (MODE == M_F64 ? 1 : 4);
   const int col0 = tn * BN + wn * WN + (lane & 15);
 #pragma unroll
   for (int i = 0; i < FM; ++i)
@@ -226,7 +229,7 @@ void gemm_nt_kernel(GemmArgs g, Epi epi) {
       const int col = col0 + j * 16;
 #pragma unroll
       for (int t = 0; t < 4; ++t) {
-        const int row = row0 + i * 16 + t;
+        const int row = row0 + i * 16 + t * RSTEP;
         if (row < g.M && col < g.N) epi(row, col, acc[i][j][t]);
       }
     }

@@ -199,12 +199,19 @@ __global__ __launch_bounds__(KT) void mat_cols_kernel(const double* X, int rows,
   }
 }
 
-// Modified Gram-Schmidt, applied twice, on p columns of length d (single block).
+// Modified Gram-Schmidt, applied twice, on p columns of length d (single
+// block).  A column whose residual after projection falls below 1e-10 of its
+// norm before projection is numerically dependent on the previous ones (the
+// weighted PSF can have rank below p); it is set to zero instead of
+// normalising rounding noise, which would not be orthogonal to the span.
 __global__ __launch_bounds__(ST) void mgs2_kernel(double* Y, int p, int d) {
-  __shared__ double sh[32];
+  __shared__ double sh[2 * 32];
   for (int pass = 0; pass < 2; ++pass) {
     for (int c = 0; c < p; ++c) {
       double* yc = Y + (long)c * d;
+      double v0[1] = {0.0};
+      for (int t = threadIdx.x; t < d; t += ST) v0[0] += yc[t] * yc[t];
+      block_allreduce<1>(v0, sh);
       for (int c2 = 0; c2 < c; ++c2) {
         const double* y2 = Y + (long)c2 * d;
         double v[1] = {0.0};
@@ -216,7 +223,7 @@ __global__ __launch_bounds__(ST) void mgs2_kernel(double* Y, int p, int d) {
       double v[1] = {0.0};
       for (int t = threadIdx.x; t < d; t += ST) v[0] += yc[t] * yc[t];
       block_allreduce<1>(v, sh);
-      const double inv = v[0] > 0.0 ? 1.0 / sqrt(v[0]) : 0.0;
+      const double inv = (v[0] > 1e-20 * v0[0] && v[0] > 0.0) ? 1.0 / sqrt(v[0]) : 0.0;
       for (int t = threadIdx.x; t < d; t += ST) yc[t] *= inv;
       __syncthreads();
     }
@@ -254,7 +261,7 @@ __global__ __launch_bounds__(ST) void jacobi_kernel(double* Z, int p, int d, dou
           continue;
         }
         const double zeta = (beta - alpha) / (2.0 * gam);
-        const double tt = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+        const double tt = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + hypot(1.0, zeta));
         const double cs = 1.0 / sqrt(1.0 + tt * tt);
         const double sn = cs * tt;
         for (int t = threadIdx.x; t < d; t += ST) {

@@ -8,7 +8,13 @@ library consume exactly the arrays produced here.
 """
 
 from .inputs import (  # noqa: F401
+    BC_REFLEXIVE,
+    BC_ZERO,
     CONFIGS,
+    SEED_BATCH,
+    SEED_IMAGE,
+    SEED_NOISE,
+    SEED_POWER,
     Problem,
     add_noise,
     blur,
