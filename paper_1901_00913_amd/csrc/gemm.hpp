@@ -10,9 +10,8 @@
 //
 // One workgroup computes a BM x BN tile with (BM/WM) x (BN/WN) wavefronts of
 // 64 lanes; each wave owns a WM x WN sub-tile made of 16x16 MFMA blocks.  K is
-// walked in stages of 128 bytes per row, double-buffered in LDS with a
-// 16-byte row pad (rows 144 bytes apart), which keeps the 16-lane column
-// reads of a fragment on distinct banks.
+// walked in stages of 64 bytes per row through an NS-deep ring of LDS
+// buffers filled by direct global-to-LDS loads (see gemm_nt_kernel).
 //
 // Every mode consumes a 16-byte chunk per lane per 64-byte K segment:
 //   BF16/FP16 : 8 values  -> one v_mfma_f32_16x16x32_{bf16,f16}
@@ -98,23 +97,159 @@ __device__ __forceinline__ void map_tile(int bid, int nblk, int tiles_m, int til
   tn = inner / gm;
 }
 
-template <int MODE, int BM, int BN, int WM, int WN, class Epi>
+
+// Fragment loads of one stage: P planes x (FM A + FN B) 16-byte LDS reads,
+// issued back to back in one asm block that ends with its own lgkmcnt wait,
+// so every read has retired when the block ends.  Keeping these reads out of
+// the compiler's sight stops its conservative wait on the in-flight
+// global-to-LDS loads of later stages (their ordering is enforced by the
+// explicit vmcnt wait and barrier at the top of each stage).
+template <int P, int FM, int FN> struct FragLoad;
+
+#define SF_R(o, a, off) "ds_read_b128 %" #o ", %" #a " offset:" #off "\n\t"
+template <> struct FragLoad<1, 4, 2> {
+  static __device__ __forceinline__ void run(uint4 (&fa)[4][1], uint4 (&fb)[2][1], const unsigned (&ra)[1],
+                                             const unsigned (&rb)[1]) {
+    asm volatile(SF_R(0, 6, 0) SF_R(1, 6, 1024) SF_R(2, 6, 2048) SF_R(3, 6, 3072) SF_R(4, 7, 0) SF_R(5, 7, 1024)
+                 "s_waitcnt lgkmcnt(0)"
+                 : "=&v"(fa[0][0]), "=&v"(fa[1][0]), "=&v"(fa[2][0]), "=&v"(fa[3][0]), "=&v"(fb[0][0]), "=&v"(fb[1][0])
+                 : "v"(ra[0]), "v"(rb[0])
+                 : "memory");
+  }
+};
+template <> struct FragLoad<2, 4, 2> {
+  static __device__ __forceinline__ void run(uint4 (&fa)[4][2], uint4 (&fb)[2][2], const unsigned (&ra)[2],
+                                             const unsigned (&rb)[2]) {
+    asm volatile(SF_R(0, 12, 0) SF_R(1, 12, 1024) SF_R(2, 12, 2048) SF_R(3, 12, 3072) SF_R(4, 13, 0)
+                 SF_R(5, 13, 1024) SF_R(6, 14, 0) SF_R(7, 14, 1024) SF_R(8, 14, 2048) SF_R(9, 14, 3072)
+                 SF_R(10, 15, 0) SF_R(11, 15, 1024)
+                 "s_waitcnt lgkmcnt(0)"
+                 : "=&v"(fa[0][0]), "=&v"(fa[1][0]), "=&v"(fa[2][0]), "=&v"(fa[3][0]), "=&v"(fb[0][0]), "=&v"(fb[1][0]),
+                   "=&v"(fa[0][1]), "=&v"(fa[1][1]), "=&v"(fa[2][1]), "=&v"(fa[3][1]), "=&v"(fb[0][1]), "=&v"(fb[1][1])
+                 : "v"(ra[0]), "v"(rb[0]), "v"(ra[1]), "v"(rb[1])
+                 : "memory");
+  }
+};
+template <> struct FragLoad<1, 4, 4> {
+  static __device__ __forceinline__ void run(uint4 (&fa)[4][1], uint4 (&fb)[4][1], const unsigned (&ra)[1],
+                                             const unsigned (&rb)[1]) {
+    asm volatile(SF_R(0, 8, 0) SF_R(1, 8, 1024) SF_R(2, 8, 2048) SF_R(3, 8, 3072) SF_R(4, 9, 0) SF_R(5, 9, 1024)
+                 SF_R(6, 9, 2048) SF_R(7, 9, 3072)
+                 "s_waitcnt lgkmcnt(0)"
+                 : "=&v"(fa[0][0]), "=&v"(fa[1][0]), "=&v"(fa[2][0]), "=&v"(fa[3][0]), "=&v"(fb[0][0]), "=&v"(fb[1][0]),
+                   "=&v"(fb[2][0]), "=&v"(fb[3][0])
+                 : "v"(ra[0]), "v"(rb[0])
+                 : "memory");
+  }
+};
+template <> struct FragLoad<2, 4, 4> {
+  static __device__ __forceinline__ void run(uint4 (&fa)[4][2], uint4 (&fb)[4][2], const unsigned (&ra)[2],
+                                             const unsigned (&rb)[2]) {
+    asm volatile(SF_R(0, 16, 0) SF_R(1, 16, 1024) SF_R(2, 16, 2048) SF_R(3, 16, 3072) SF_R(4, 17, 0)
+                 SF_R(5, 17, 1024) SF_R(6, 17, 2048) SF_R(7, 17, 3072) SF_R(8, 18, 0) SF_R(9, 18, 1024)
+                 SF_R(10, 18, 2048) SF_R(11, 18, 3072) SF_R(12, 19, 0) SF_R(13, 19, 1024) SF_R(14, 19, 2048)
+                 SF_R(15, 19, 3072)
+                 "s_waitcnt lgkmcnt(0)"
+                 : "=&v"(fa[0][0]), "=&v"(fa[1][0]), "=&v"(fa[2][0]), "=&v"(fa[3][0]), "=&v"(fb[0][0]), "=&v"(fb[1][0]),
+                   "=&v"(fb[2][0]), "=&v"(fb[3][0]), "=&v"(fa[0][1]), "=&v"(fa[1][1]), "=&v"(fa[2][1]), "=&v"(fa[3][1]),
+                   "=&v"(fb[0][1]), "=&v"(fb[1][1]), "=&v"(fb[2][1]), "=&v"(fb[3][1])
+                 : "v"(ra[0]), "v"(rb[0]), "v"(ra[1]), "v"(rb[1])
+                 : "memory");
+  }
+};
+template <> struct FragLoad<1, 2, 4> {
+  static __device__ __forceinline__ void run(uint4 (&fa)[2][1], uint4 (&fb)[4][1], const unsigned (&ra)[1],
+                                             const unsigned (&rb)[1]) {
+    asm volatile(SF_R(0, 6, 0) SF_R(1, 6, 1024) SF_R(2, 7, 0) SF_R(3, 7, 1024) SF_R(4, 7, 2048) SF_R(5, 7, 3072)
+                 "s_waitcnt lgkmcnt(0)"
+                 : "=&v"(fa[0][0]), "=&v"(fa[1][0]), "=&v"(fb[0][0]), "=&v"(fb[1][0]), "=&v"(fb[2][0]), "=&v"(fb[3][0])
+                 : "v"(ra[0]), "v"(rb[0])
+                 : "memory");
+  }
+};
+template <> struct FragLoad<2, 2, 4> {
+  static __device__ __forceinline__ void run(uint4 (&fa)[2][2], uint4 (&fb)[4][2], const unsigned (&ra)[2],
+                                             const unsigned (&rb)[2]) {
+    asm volatile(SF_R(0, 12, 0) SF_R(1, 12, 1024) SF_R(2, 13, 0) SF_R(3, 13, 1024) SF_R(4, 13, 2048)
+                 SF_R(5, 13, 3072) SF_R(6, 14, 0) SF_R(7, 14, 1024) SF_R(8, 15, 0) SF_R(9, 15, 1024)
+                 SF_R(10, 15, 2048) SF_R(11, 15, 3072)
+                 "s_waitcnt lgkmcnt(0)"
+                 : "=&v"(fa[0][0]), "=&v"(fa[1][0]), "=&v"(fb[0][0]), "=&v"(fb[1][0]), "=&v"(fb[2][0]), "=&v"(fb[3][0]),
+                   "=&v"(fa[0][1]), "=&v"(fa[1][1]), "=&v"(fb[0][1]), "=&v"(fb[1][1]), "=&v"(fb[2][1]), "=&v"(fb[3][1])
+                 : "v"(ra[0]), "v"(rb[0]), "v"(ra[1]), "v"(rb[1])
+                 : "memory");
+  }
+};
+template <> struct FragLoad<1, 2, 2> {
+  static __device__ __forceinline__ void run(uint4 (&fa)[2][1], uint4 (&fb)[2][1], const unsigned (&ra)[1],
+                                             const unsigned (&rb)[1]) {
+    asm volatile(SF_R(0, 4, 0) SF_R(1, 4, 1024) SF_R(2, 5, 0) SF_R(3, 5, 1024)
+                 "s_waitcnt lgkmcnt(0)"
+                 : "=&v"(fa[0][0]), "=&v"(fa[1][0]), "=&v"(fb[0][0]), "=&v"(fb[1][0])
+                 : "v"(ra[0]), "v"(rb[0])
+                 : "memory");
+  }
+};
+template <> struct FragLoad<2, 2, 2> {
+  static __device__ __forceinline__ void run(uint4 (&fa)[2][2], uint4 (&fb)[2][2], const unsigned (&ra)[2],
+                                             const unsigned (&rb)[2]) {
+    asm volatile(SF_R(0, 8, 0) SF_R(1, 8, 1024) SF_R(2, 9, 0) SF_R(3, 9, 1024) SF_R(4, 10, 0) SF_R(5, 10, 1024)
+                 SF_R(6, 11, 0) SF_R(7, 11, 1024)
+                 "s_waitcnt lgkmcnt(0)"
+                 : "=&v"(fa[0][0]), "=&v"(fa[1][0]), "=&v"(fb[0][0]), "=&v"(fb[1][0]), "=&v"(fa[0][1]), "=&v"(fa[1][1]),
+                   "=&v"(fb[0][1]), "=&v"(fb[1][1])
+                 : "v"(ra[0]), "v"(rb[0]), "v"(ra[1]), "v"(rb[1])
+                 : "memory");
+  }
+};
+#undef SF_R
+
+// 32-bit LDS address of a pointer into __shared__ memory.
+__device__ __forceinline__ unsigned lds_addr(const void* p) {
+  return static_cast<unsigned>(reinterpret_cast<uintptr_t>((const __attribute__((address_space(3))) void*)p));
+}
+
+__device__ __forceinline__ int swz(int r) { return ((r >> 1) ^ (r >> 3)) & 3; }
+
+// s_waitcnt immediate that waits until at most N vector-memory operations
+// are outstanding (expcnt and lgkmcnt left at their no-wait maxima).
+template <int N>
+constexpr int vmcnt_imm() {
+  static_assert(N >= 0 && N < 64, "vmcnt range");
+  return (N & 0xF) | (0x7 << 4) | (0xF << 8) | ((N >> 4) << 14);
+}
+
+// LDS staging: NS stages, each holding 64 bytes of K for the BM + BN rows of
+// every plane.  Rows are 64 bytes apart with no padding; the four 16-byte
+// chunks of row r are XOR-swizzled: chunk c lives at c ^ f(r & 15) with
+// f(r) = ((r >> 1) ^ (r >> 3)) & 3.  The 16 rows read by one fragment load
+// then land on 16 distinct 16-byte slots of a 256-byte bank window, and each
+// half of them on 8 distinct slots of a 128-byte window.
+//
+// Global -> LDS uses gfx950's global_load_lds_dwordx4: one instruction moves
+// 16 rows x 64 bytes (lane L writes LDS bytes [16 L, 16 L + 16)), with lane L
+// fetching the logical chunk that the swizzle places at its slot.  Loads run
+// NS - 1 stages ahead; each stage starts with a wait until the wave's loads of
+// that stage have landed and a workgroup barrier that publishes all waves'
+// loads (and retires every wave's reads of the stage about to be refilled).
+template <int MODE, int BM, int BN, int WM, int WN, int NS, class Epi>
 __global__ __launch_bounds__((BM / WM) * (BN / WN) * 64, 1)
 void gemm_nt_kernel(GemmArgs g, Epi epi) {
   using Tr = ModeTraits<MODE>;
   using AccT = typename AccVec<MODE>::T;
   constexpr int P = Tr::planes;
   constexpr int WAVES_N = BN / WN;
-  constexpr int NT = (BM / WM) * WAVES_N * 64;
-  constexpr int ROWB = 128;                 // K bytes per row per stage
-  constexpr int PITCH = ROWB + 16;          // padded LDS row
-  constexpr int TILEB = (BM + BN) * PITCH;  // bytes per plane per stage
-  constexpr int CA = BM * (ROWB / 16) / NT; // A chunks per thread per plane
-  constexpr int CB = BN * (ROWB / 16) / NT;
+  constexpr int NW = (BM / WM) * WAVES_N;
+  constexpr int SEGB = 64;                    // K bytes per row per stage
+  constexpr int ROWS = BM + BN;
+  constexpr int PLANEB = ROWS * SEGB;         // bytes per plane per stage
+  constexpr int STAGEB = P * PLANEB;
+  constexpr int NINS = P * ROWS / 16;         // 16-row load instructions per stage
+  constexpr int IPW = NINS / NW;              // per wave
   constexpr int FM = WM / 16, FN = WN / 16;
-  static_assert(BM * (ROWB / 16) % NT == 0 && BN * (ROWB / 16) % NT == 0, "tile/threads");
+  static_assert(NINS % NW == 0 && BM % 16 == 0 && BN % 16 == 0 && NS >= 2, "tile/waves/stages");
 
-  extern __shared__ __attribute__((aligned(16))) unsigned char lds[];
+  __shared__ __attribute__((aligned(16))) unsigned char lds[NS * STAGEB];
 
   const int tiles_m = (g.M + BM - 1) / BM;
   const int tiles_n = (g.N + BN - 1) / BN;
@@ -126,55 +261,41 @@ void gemm_nt_kernel(GemmArgs g, Epi epi) {
   const int wave = tid >> 6;
   const int wm = wave / WAVES_N;
   const int wn = wave - wm * WAVES_N;
+  const int ktiles = (g.K * Tr::esize + SEGB - 1) / SEGB;
 
-  const long lda_b = g.lda * Tr::esize;
-  const long ldb_b = g.ldb * Tr::esize;
-  const int ktiles = (g.K * Tr::esize + ROWB - 1) / ROWB;
-
-  // Per-thread global source pointers (advance by ROWB per stage).
-  const unsigned char* pa[P][CA];
-  const unsigned char* pb[P][CB];
-  int la[CA], lb[CB];
+  // This wave's load instructions: global source of its lane and the LDS
+  // offset (inside a stage) of the 16-row group.
+  const unsigned char* src[IPW];
+  int dst[IPW];
+  {
+    const int lrow = lane >> 2;
+    const int chunk = (lane & 3) ^ swz(lrow);
 #pragma unroll
-  for (int i = 0; i < CA; ++i) {
-    const int c = tid + i * NT;
-    const int row = c >> 3, cc = c & 7;
-    la[i] = row * PITCH + cc * 16;
-#pragma unroll
-    for (int p = 0; p < P; ++p)
-      pa[p][i] = static_cast<const unsigned char*>(g.a[p]) + (long)(tm * BM + row) * lda_b + cc * 16;
-  }
-#pragma unroll
-  for (int i = 0; i < CB; ++i) {
-    const int c = tid + i * NT;
-    const int row = c >> 3, cc = c & 7;
-    lb[i] = (BM + row) * PITCH + cc * 16;
-#pragma unroll
-    for (int p = 0; p < P; ++p)
-      pb[p][i] = static_cast<const unsigned char*>(g.b[p]) + (long)(tn * BN + row) * ldb_b + cc * 16;
+    for (int i = 0; i < IPW; ++i) {
+      const int q = wave + NW * i;
+      const int p = q / (ROWS / 16);
+      const int rg = q - p * (ROWS / 16);
+      const int row = rg * 16 + lrow;
+      const unsigned char* base;
+      if (row < BM)
+        base = static_cast<const unsigned char*>(g.a[p]) + (long)(tm * BM + row) * (g.lda * Tr::esize);
+      else
+        base = static_cast<const unsigned char*>(g.b[p]) + (long)(tn * BN + row - BM) * (g.ldb * Tr::esize);
+      src[i] = base + chunk * 16;
+      dst[i] = p * PLANEB + rg * 16 * SEGB;
+    }
   }
 
-  uint4 sa[P][CA], sb[P][CB];
-  auto gload = [&](int kt) {
-    const long off = (long)kt * ROWB;
-#pragma unroll
-    for (int p = 0; p < P; ++p) {
-#pragma unroll
-      for (int i = 0; i < CA; ++i) sa[p][i] = *reinterpret_cast<const uint4*>(pa[p][i] + off);
-#pragma unroll
-      for (int i = 0; i < CB; ++i) sb[p][i] = *reinterpret_cast<const uint4*>(pb[p][i] + off);
-    }
-  };
-  auto lstore = [&](int buf) {
-#pragma unroll
-    for (int p = 0; p < P; ++p) {
-      unsigned char* base = lds + (buf * P + p) * TILEB;
-#pragma unroll
-      for (int i = 0; i < CA; ++i) *reinterpret_cast<uint4*>(base + la[i]) = sa[p][i];
-#pragma unroll
-      for (int i = 0; i < CB; ++i) *reinterpret_cast<uint4*>(base + lb[i]) = sb[p][i];
-    }
-  };
+#define SF_ISSUE_STAGE(KSTAGE, BUF)                                                                  \
+  {                                                                                                  \
+    const long koff_ = (long)(KSTAGE) * SEGB;                                                        \
+    unsigned char* sbase_ = lds + (BUF) * STAGEB;                                                    \
+    _Pragma("unroll") for (int i_ = 0; i_ < IPW; ++i_) {                                             \
+      __builtin_amdgcn_global_load_lds(                                                              \
+          (const void __attribute__((address_space(1)))*)(src[i_] + koff_),                          \
+          (void __attribute__((address_space(3)))*)(sbase_ + dst[i_]), 16, 0, 0);                    \
+    }                                                                                                \
+  }
 
   AccT acc[FM][FN];
 #pragma unroll
@@ -182,41 +303,45 @@ void gemm_nt_kernel(GemmArgs g, Epi epi) {
 #pragma unroll
     for (int j = 0; j < FN; ++j) acc[i][j] = AccT{0, 0, 0, 0};
 
-  // fragment read offsets inside a stage
+  // fragment reads: lane reads logical chunk (lane >> 4) of row (lane & 15)
+  // of each 16-row block; the swizzle term depends only on (lane & 15).
   const int frow = lane & 15;
-  const int fchunk = (lane >> 4) * 16;
-  const int a_off = (wm * WM + frow) * PITCH + fchunk;
-  const int b_off = (BM + wn * WN + frow) * PITCH + fchunk;
+  const int fchunk = ((lane >> 4) ^ swz(frow)) * 16;
+  const int a_off = (wm * WM + frow) * SEGB + fchunk;
+  const int b_off = (BM + wn * WN + frow) * SEGB + fchunk;
 
-  gload(0);
-  lstore(0);
-  __syncthreads();
+#pragma unroll
+  for (int st = 0; st < NS - 1; ++st) SF_ISSUE_STAGE(min(st, ktiles - 1), st);
 
   for (int kt = 0; kt < ktiles; ++kt) {
-    const int buf = kt & 1;
-    const bool more = (kt + 1) < ktiles;
-    if (more) gload(kt + 1);
-#pragma unroll
-    for (int seg = 0; seg < ROWB / 64; ++seg) {
-      uint4 fa[FM][P], fb[FN][P];
+    // the loads of stage kt are done when at most (NS - 2) stages remain in flight
+    __builtin_amdgcn_s_waitcnt(vmcnt_imm<(NS - 2) * IPW>());
+    __builtin_amdgcn_s_barrier();
+    asm volatile("" ::: "memory");
+    const unsigned char* sbase = lds + (kt % NS) * STAGEB;
+    uint4 fa[FM][P], fb[FN][P];
+    {
+      unsigned ra[P], rb[P];
 #pragma unroll
       for (int p = 0; p < P; ++p) {
-        const unsigned char* base = lds + (buf * P + p) * TILEB + seg * 64;
-#pragma unroll
-        for (int i = 0; i < FM; ++i)
-          fa[i][p] = *reinterpret_cast<const uint4*>(base + a_off + i * 16 * PITCH);
-#pragma unroll
-        for (int j = 0; j < FN; ++j)
-          fb[j][p] = *reinterpret_cast<const uint4*>(base + b_off + j * 16 * PITCH);
+        ra[p] = lds_addr(sbase + p * PLANEB + a_off);
+        rb[p] = lds_addr(sbase + p * PLANEB + b_off);
       }
-#pragma unroll
-      for (int i = 0; i < FM; ++i)
-#pragma unroll
-        for (int j = 0; j < FN; ++j) mma_chunk<MODE>(acc[i][j], fa[i], fb[j]);
+      FragLoad<P, FM, FN>::run(fa, fb, ra, rb);
     }
-    if (more) lstore(buf ^ 1);
-    __syncthreads();
+    // refill the buffer every wave finished reading before the barrier
+    {
+      const int nb = (kt + NS - 1) % NS;
+      SF_ISSUE_STAGE(min(kt + NS - 1, ktiles - 1), nb);
+    }
+#pragma unroll
+    for (int i = 0; i < FM; ++i)
+#pragma unroll
+      for (int j = 0; j < FN; ++j) mma_chunk<MODE>(acc[i][j], fa[i], fb[j]);
+    asm volatile("" ::: "memory");
   }
+  __builtin_amdgcn_s_waitcnt(vmcnt_imm<0>());
+#undef SF_ISSUE_STAGE
 
   // epilogue
   constexpr int RSTEP = (MODE == M_F64) ? 4 : 1;          // row stride between accumulator registers
@@ -236,33 +361,34 @@ void gemm_nt_kernel(GemmArgs g, Epi epi) {
 }
 
 // Tile configuration of the single kernel family.
+#ifndef SF_TILE_BM
+#define SF_TILE_BM 128
+#define SF_TILE_BN 128
+#define SF_TILE_WM 64
+#define SF_TILE_WN 32
+#define SF_TILE_NS 4
+#endif
 struct TileCfg {
-  static constexpr int BM = 128, BN = 128, WM = 64, WN = 64;
-  static constexpr int ROW_PAD = 256;   // operand row allocations are multiples of this
-  static constexpr int K_PAD = 64;      // operand leading dimensions are multiples of this
+  static constexpr int BM = SF_TILE_BM, BN = SF_TILE_BN, WM = SF_TILE_WM, WN = SF_TILE_WN;
+  static constexpr int NS = SF_TILE_NS;   // LDS pipeline stages of 64 K-bytes
+  static constexpr int ROW_PAD = 256;     // operand row allocations are multiples of this
+  static constexpr int K_PAD = 64;        // operand leading dimensions are multiples of this
+  static_assert(BM <= ROW_PAD && BN <= ROW_PAD, "row padding must cover a tile");
 };
 
 template <int MODE>
 constexpr size_t gemm_lds_bytes() {
-  return 2ull * ModeTraits<MODE>::planes * (TileCfg::BM + TileCfg::BN) * (128 + 16);
+  return (size_t)TileCfg::NS * ModeTraits<MODE>::planes * (TileCfg::BM + TileCfg::BN) * 64;
 }
 
 template <int MODE, class Epi>
 hipError_t launch_gemm(const GemmArgs& g, const Epi& epi, hipStream_t s) {
   constexpr int BM = TileCfg::BM, BN = TileCfg::BN, WM = TileCfg::WM, WN = TileCfg::WN;
-  auto kern = gemm_nt_kernel<MODE, BM, BN, WM, WN, Epi>;
-  static bool attr_set = false;
-  constexpr size_t lds = gemm_lds_bytes<MODE>();
-  if (!attr_set) {
-    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    if (e != hipSuccess) return e;
-    attr_set = true;
-  }
+  auto kern = gemm_nt_kernel<MODE, BM, BN, WM, WN, TileCfg::NS, Epi>;   // LDS is static (gemm_lds_bytes)
   if (g.M <= 0 || g.N <= 0) return hipSuccess;
   const int tiles = ((g.M + BM - 1) / BM) * ((g.N + BN - 1) / BN);
   constexpr int threads = (BM / WM) * (BN / WN) * 64;
-  hipLaunchKernelGGL(kern, dim3(tiles), dim3(threads), lds, s, g, epi);
+  hipLaunchKernelGGL(kern, dim3(tiles), dim3(threads), 0, s, g, epi);
   return hipGetLastError();
 }
 
