@@ -41,6 +41,7 @@ struct GemmArgs {
   const void* b[2];   // B planes
   long lda, ldb;      // leading dimensions in elements
   int M, N, K;
+  int kchunk;         // K stages (64 bytes) per split; split z = blockIdx.y covers [z kchunk, (z+1) kchunk)
 };
 
 template <int MODE> struct AccVec { using T = f32x4_t; };
@@ -232,7 +233,7 @@ constexpr int vmcnt_imm() {
 // NS - 1 stages ahead; each stage starts with a wait until the wave's loads of
 // that stage have landed and a workgroup barrier that publishes all waves'
 // loads (and retires every wave's reads of the stage about to be refilled).
-template <int MODE, int BM, int BN, int WM, int WN, int NS, class Epi>
+template <int MODE, int BM, int BN, int WM, int WN, int NS, int G, class Epi>
 __global__ __launch_bounds__((BM / WM) * (BN / WN) * 64, 1)
 void gemm_nt_kernel(GemmArgs g, Epi epi) {
   using Tr = ModeTraits<MODE>;
@@ -247,7 +248,8 @@ void gemm_nt_kernel(GemmArgs g, Epi epi) {
   constexpr int NINS = P * ROWS / 16;         // 16-row load instructions per stage
   constexpr int IPW = NINS / NW;              // per wave
   constexpr int FM = WM / 16, FN = WN / 16;
-  static_assert(NINS % NW == 0 && BM % 16 == 0 && BN % 16 == 0 && NS >= 2, "tile/waves/stages");
+  static_assert(NINS % NW == 0 && BM % 16 == 0 && BN % 16 == 0, "tile/waves");
+  static_assert(G >= 1 && NS >= 2 * G && NS % G == 0, "stages per barrier");
 
   __shared__ __attribute__((aligned(16))) unsigned char lds[NS * STAGEB];
 
@@ -261,7 +263,9 @@ void gemm_nt_kernel(GemmArgs g, Epi epi) {
   const int wave = tid >> 6;
   const int wm = wave / WAVES_N;
   const int wn = wave - wm * WAVES_N;
-  const int ktiles = (g.K * Tr::esize + SEGB - 1) / SEGB;
+  const int ktot = (g.K * Tr::esize + SEGB - 1) / SEGB;
+  const int kt0 = blockIdx.y * g.kchunk;
+  const int ktiles = min(ktot - kt0, g.kchunk);   // >= 1 by construction of the split
 
   // This wave's load instructions: global source of its lane and the LDS
   // offset (inside a stage) of the 16-row group.
@@ -281,7 +285,7 @@ void gemm_nt_kernel(GemmArgs g, Epi epi) {
         base = static_cast<const unsigned char*>(g.a[p]) + (long)(tm * BM + row) * (g.lda * Tr::esize);
       else
         base = static_cast<const unsigned char*>(g.b[p]) + (long)(tn * BN + row - BM) * (g.ldb * Tr::esize);
-      src[i] = base + chunk * 16;
+      src[i] = base + (long)kt0 * SEGB + chunk * 16;
       dst[i] = p * PLANEB + rg * 16 * SEGB;
     }
   }
@@ -310,34 +314,44 @@ void gemm_nt_kernel(GemmArgs g, Epi epi) {
   const int a_off = (wm * WM + frow) * SEGB + fchunk;
   const int b_off = (BM + wn * WN + frow) * SEGB + fchunk;
 
+  // Stages are consumed G at a time per barrier: iteration `it` computes
+  // stages [it G, it G + G).  Loads run NS - G stages ahead of the first
+  // stage consumed; at the top of an iteration NS - 2G stages may remain in
+  // flight.  Stage indices past the end are clamped (the re-read lands in a
+  // buffer that is never consumed again).
 #pragma unroll
-  for (int st = 0; st < NS - 1; ++st) SF_ISSUE_STAGE(min(st, ktiles - 1), st);
+  for (int st = 0; st < NS - G; ++st) SF_ISSUE_STAGE(min(st, ktiles - 1), st);
 
-  for (int kt = 0; kt < ktiles; ++kt) {
-    // the loads of stage kt are done when at most (NS - 2) stages remain in flight
-    __builtin_amdgcn_s_waitcnt(vmcnt_imm<(NS - 2) * IPW>());
+  const int iters = (ktiles + G - 1) / G;
+  for (int it = 0; it < iters; ++it) {
+    __builtin_amdgcn_s_waitcnt(vmcnt_imm<(NS - 2 * G) * IPW>());
     __builtin_amdgcn_s_barrier();
     asm volatile("" ::: "memory");
-    const unsigned char* sbase = lds + (kt % NS) * STAGEB;
-    uint4 fa[FM][P], fb[FN][P];
-    {
-      unsigned ra[P], rb[P];
 #pragma unroll
-      for (int p = 0; p < P; ++p) {
-        ra[p] = lds_addr(sbase + p * PLANEB + a_off);
-        rb[p] = lds_addr(sbase + p * PLANEB + b_off);
+    for (int gg = 0; gg < G; ++gg) {
+      const int kst = it * G + gg + NS - G;
+      SF_ISSUE_STAGE(min(kst, ktiles - 1), kst % NS);
+    }
+#pragma unroll
+    for (int gg = 0; gg < G; ++gg) {
+      const int kt = it * G + gg;
+      if (G > 1 && kt >= ktiles) break;
+      const unsigned char* sbase = lds + (kt % NS) * STAGEB;
+      uint4 fa[FM][P], fb[FN][P];
+      {
+        unsigned ra[P], rb[P];
+#pragma unroll
+        for (int p = 0; p < P; ++p) {
+          ra[p] = lds_addr(sbase + p * PLANEB + a_off);
+          rb[p] = lds_addr(sbase + p * PLANEB + b_off);
+        }
+        FragLoad<P, FM, FN>::run(fa, fb, ra, rb);
       }
-      FragLoad<P, FM, FN>::run(fa, fb, ra, rb);
-    }
-    // refill the buffer every wave finished reading before the barrier
-    {
-      const int nb = (kt + NS - 1) % NS;
-      SF_ISSUE_STAGE(min(kt + NS - 1, ktiles - 1), nb);
-    }
 #pragma unroll
-    for (int i = 0; i < FM; ++i)
+      for (int i = 0; i < FM; ++i)
 #pragma unroll
-      for (int j = 0; j < FN; ++j) mma_chunk<MODE>(acc[i][j], fa[i], fb[j]);
+        for (int j = 0; j < FN; ++j) mma_chunk<MODE>(acc[i][j], fa[i], fb[j]);
+    }
     asm volatile("" ::: "memory");
   }
   __builtin_amdgcn_s_waitcnt(vmcnt_imm<0>());
@@ -366,11 +380,15 @@ void gemm_nt_kernel(GemmArgs g, Epi epi) {
 #define SF_TILE_BN 128
 #define SF_TILE_WM 64
 #define SF_TILE_WN 32
-#define SF_TILE_NS 4
+#define SF_TILE_NS 2
+#endif
+#ifndef SF_TILE_G
+#define SF_TILE_G 1
 #endif
 struct TileCfg {
   static constexpr int BM = SF_TILE_BM, BN = SF_TILE_BN, WM = SF_TILE_WM, WN = SF_TILE_WN;
   static constexpr int NS = SF_TILE_NS;   // LDS pipeline stages of 64 K-bytes
+  static constexpr int G = SF_TILE_G;     // stages consumed per barrier
   static constexpr int ROW_PAD = 256;     // operand row allocations are multiples of this
   static constexpr int K_PAD = 64;        // operand leading dimensions are multiples of this
   static_assert(BM <= ROW_PAD && BN <= ROW_PAD, "row padding must cover a tile");
@@ -381,14 +399,66 @@ constexpr size_t gemm_lds_bytes() {
   return (size_t)TileCfg::NS * ModeTraits<MODE>::planes * (TileCfg::BM + TileCfg::BN) * 64;
 }
 
+// Partial product of one K split, stored for the reduction.
+template <int MODE>
+struct EpiPartial {
+  typename ModeTraits<MODE>::Acc* ws;
+  int M, N;
+  __device__ __forceinline__ void operator()(int row, int col, typename ModeTraits<MODE>::Acc v) const {
+    ws[((long)blockIdx.y * M + row) * N + col] = v;
+  }
+};
+
+// Sums the K-split partials in split order (deterministic) and applies the
+// GEMM's own epilogue element-wise.
+template <class Acc, class Epi>
+__global__ void splitk_reduce_kernel(const Acc* ws, int S, int M, int N, Epi epi) {
+  const long total = (long)M * N;
+  for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < total; e += (long)gridDim.x * blockDim.x) {
+    Acc v = ws[e];
+    for (int z = 1; z < S; ++z) v += ws[z * total + e];
+    const int row = (int)(e / N);
+    epi(row, (int)(e - (long)row * N), v);
+  }
+}
+
+template <int MODE>
+inline int gemm_kstages(int K) { return (K * ModeTraits<MODE>::esize + 63) / 64; }
+
+// Number of K splits for an M x N x K product: enough workgroups to fill
+// `slots` (CUs x resident blocks per CU), keeping at least 16 K stages per split.
+template <int MODE>
+inline int choose_splitk(int M, int N, int K, int slots) {
+  const int tiles = ((M + TileCfg::BM - 1) / TileCfg::BM) * ((N + TileCfg::BN - 1) / TileCfg::BN);
+  const int kst = gemm_kstages<MODE>(K);
+  int S = 1;
+  while (S < 16 && tiles * S * 2 <= slots && kst / (S * 2) >= 16) S *= 2;
+  return S;
+}
+
+// Launch; with S > 1 the partials go to `ws` (S x M x N accumulator values)
+// and the reduction applies `epi`.
 template <int MODE, class Epi>
-hipError_t launch_gemm(const GemmArgs& g, const Epi& epi, hipStream_t s) {
+hipError_t launch_gemm(GemmArgs g, const Epi& epi, hipStream_t s, int S = 1,
+                       typename ModeTraits<MODE>::Acc* ws = nullptr) {
   constexpr int BM = TileCfg::BM, BN = TileCfg::BN, WM = TileCfg::WM, WN = TileCfg::WN;
-  auto kern = gemm_nt_kernel<MODE, BM, BN, WM, WN, TileCfg::NS, Epi>;   // LDS is static (gemm_lds_bytes)
   if (g.M <= 0 || g.N <= 0) return hipSuccess;
   const int tiles = ((g.M + BM - 1) / BM) * ((g.N + BN - 1) / BN);
   constexpr int threads = (BM / WM) * (BN / WN) * 64;
-  hipLaunchKernelGGL(kern, dim3(tiles), dim3(threads), 0, s, g, epi);
+  const int kst = gemm_kstages<MODE>(g.K);
+  if (S <= 1 || !ws) {
+    g.kchunk = kst;
+    hipLaunchKernelGGL((gemm_nt_kernel<MODE, BM, BN, WM, WN, TileCfg::NS, TileCfg::G, Epi>), dim3(tiles),
+                       dim3(threads), 0, s, g, epi);
+    return hipGetLastError();
+  }
+  g.kchunk = (kst + S - 1) / S;
+  S = (kst + g.kchunk - 1) / g.kchunk;   // every split non-empty
+  EpiPartial<MODE> part{ws, g.M, g.N};
+  hipLaunchKernelGGL((gemm_nt_kernel<MODE, BM, BN, WM, WN, TileCfg::NS, TileCfg::G, EpiPartial<MODE>>),
+                     dim3(tiles, S), dim3(threads), 0, s, g, part);
+  hipLaunchKernelGGL((splitk_reduce_kernel<typename ModeTraits<MODE>::Acc, Epi>), dim3(2048), dim3(256), 0, s,
+                     ws, S, g.M, g.N, epi);
   return hipGetLastError();
 }
 

@@ -30,6 +30,8 @@ struct sfista_plan {
   void* st[2] = {};
   double* aux = nullptr;      // m x n FP64 scratch (power iterate, copies)
   double* red = nullptr;      // reduction partials [RED_BLOCKS] + scalars
+  void* ws = nullptr;         // K-split partials of F2 and G2
+  int split_f2 = 1, split_g2 = 1;
   double bobs_norm = 0.0;
   // optional per-GEMM event timing
   int timing = 0;
@@ -104,6 +106,7 @@ GemmArgs gargs(void* const* a, long lda, void* const* b, long ldb, int M, int N,
   g.b[0] = b[0]; g.b[1] = b[1];
   g.lda = lda; g.ldb = ldb;
   g.M = M; g.N = N; g.K = K;
+  g.kchunk = 0;
   return g;
 }
 
@@ -122,7 +125,8 @@ hipError_t run_f2(sfista_plan* h, bool with_bobs, double* copy) {
   e.out[0] = h->R[0]; e.out[1] = h->R[1]; e.ldo = h->ldR;
   e.bobs_t = with_bobs ? static_cast<const typename ModeTraits<MODE>::Acc*>(h->bobs_t) : nullptr;
   e.m = h->m; e.copy = copy; e.n = h->n;
-  return launch_gemm<MODE>(gargs<MODE>(h->T, h->ldT, h->Bc, h->ldBc, h->n, h->m, h->r * h->m), e, h->s);
+  return launch_gemm<MODE>(gargs<MODE>(h->T, h->ldT, h->Bc, h->ldBc, h->n, h->m, h->r * h->m), e, h->s,
+                           h->split_f2, static_cast<typename ModeTraits<MODE>::Acc*>(h->ws));
 }
 
 // G1: S_k = B_k^T R for all k, stored side by side (m x rn): S[i][k n + j].
@@ -136,7 +140,8 @@ hipError_t run_g1(sfista_plan* h) {
 // G2 with an arbitrary epilogue: sum_k S_k A_k.
 template <int MODE, class Epi>
 hipError_t run_g2(sfista_plan* h, const Epi& e) {
-  return launch_gemm<MODE>(gargs<MODE>(h->S, h->ldS, h->At, h->ldAt, h->m, h->n, h->r * h->n), e, h->s);
+  return launch_gemm<MODE>(gargs<MODE>(h->S, h->ldS, h->At, h->ldAt, h->m, h->n, h->r * h->n), e, h->s,
+                           h->split_g2, static_cast<typename ModeTraits<MODE>::Acc*>(h->ws));
 }
 
 template <int MODE>
@@ -248,6 +253,21 @@ int setup_mode(sfista_plan* h, const double* Bobs, const double* A, const double
        (h->aux = static_cast<double*>(h->arena.alloc_zero((size_t)m * n * 8, h->s))) &&
        (h->red = static_cast<double*>(h->arena.alloc_zero((RED_BLOCKS + 8) * 8, h->s)));
   if (!ok) return set_error(SFISTA_ERR_NOMEM, "device allocation failed (%s)", h->arena.last_error());
+
+  // K splits for the two square products (their tile count alone can leave CUs idle)
+  {
+    int dev = 0, cus = 256;
+    if (hipGetDevice(&dev) == hipSuccess) {
+      hipDeviceProp_t prop;
+      if (hipGetDeviceProperties(&prop, dev) == hipSuccess) cus = prop.multiProcessorCount;
+    }
+    const int per_cu = (int)(160 * 1024 / gemm_lds_bytes<MODE>()) > 1 ? 2 : 1;
+    h->split_f2 = choose_splitk<MODE>(n, m, (int)rm, cus * per_cu);
+    h->split_g2 = choose_splitk<MODE>(m, n, (int)rn, cus * per_cu);
+    const int smax = h->split_f2 > h->split_g2 ? h->split_f2 : h->split_g2;
+    if (smax > 1 && !(h->ws = h->arena.alloc_zero((size_t)smax * m * n * sizeof(Acc), h->s)))
+      return set_error(SFISTA_ERR_NOMEM, "device allocation failed (%s)", h->arena.last_error());
+  }
 
   hipError_t e;
   if ((e = run_pack<MODE>(h, A, B)) != hipSuccess) return hip_fail(e, "factor packing");
