@@ -233,25 +233,36 @@ constexpr int vmcnt_imm() {
 // NS - 1 stages ahead; each stage starts with a wait until the wave's loads of
 // that stage have landed and a workgroup barrier that publishes all waves'
 // loads (and retires every wave's reads of the stage about to be refilled).
-template <int MODE, int BM, int BN, int WM, int WN, int NS, int G, class Epi>
-__global__ __launch_bounds__((BM / WM) * (BN / WN) * 64, 1)
+// Workgroup layout: KG groups of (BM/WM) x (BN/WN) waves.  Every group
+// covers the whole BM x BN tile; per barrier the workgroup consumes G
+// stages and group q computes the stages gg = q (mod KG) of them, so the K
+// range is split inside the workgroup.  After the loop the groups add their
+// accumulators through LDS and group 0 runs the epilogue.  KG = 2 lets eight
+// waves share a 128 x 128 tile with 64 x 64 sub-tiles, which halves the LDS
+// fragment traffic per MFMA compared with 64 x 32 sub-tiles.
+template <int MODE, int BM, int BN, int WM, int WN, int NS, int G, int KG, class Epi>
+__global__ __launch_bounds__(KG * (BM / WM) * (BN / WN) * 64, 1)
 void gemm_nt_kernel(GemmArgs g, Epi epi) {
   using Tr = ModeTraits<MODE>;
   using AccT = typename AccVec<MODE>::T;
+  using Acc = typename Tr::Acc;
   constexpr int P = Tr::planes;
   constexpr int WAVES_N = BN / WN;
-  constexpr int NW = (BM / WM) * WAVES_N;
+  constexpr int NWG = (BM / WM) * WAVES_N;    // waves per K group
+  constexpr int NW = KG * NWG;
   constexpr int SEGB = 64;                    // K bytes per row per stage
   constexpr int ROWS = BM + BN;
   constexpr int PLANEB = ROWS * SEGB;         // bytes per plane per stage
   constexpr int STAGEB = P * PLANEB;
   constexpr int NINS = P * ROWS / 16;         // 16-row load instructions per stage
-  constexpr int IPW = NINS / NW;              // per wave
+  constexpr int IPI = G * NINS / NW;          // load instructions per wave per barrier interval
   constexpr int FM = WM / 16, FN = WN / 16;
-  static_assert(NINS % NW == 0 && BM % 16 == 0 && BN % 16 == 0, "tile/waves");
-  static_assert(G >= 1 && NS >= 2 * G && NS % G == 0, "stages per barrier");
+  constexpr int REDB = KG > 1 ? NWG * FM * FN * 4 * 64 * (int)sizeof(Acc) : 0;
+  constexpr int LDSB = NS * STAGEB > REDB ? NS * STAGEB : REDB;
+  static_assert((G * NINS) % NW == 0 && BM % 16 == 0 && BN % 16 == 0, "tile/waves");
+  static_assert(G >= 1 && NS >= 2 * G && NS % G == 0 && G % KG == 0, "stages per barrier");
 
-  __shared__ __attribute__((aligned(16))) unsigned char lds[NS * STAGEB];
+  __shared__ __attribute__((aligned(16))) unsigned char lds[LDSB];
 
   const int tiles_m = (g.M + BM - 1) / BM;
   const int tiles_n = (g.N + BN - 1) / BN;
@@ -261,24 +272,28 @@ void gemm_nt_kernel(GemmArgs g, Epi epi) {
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wave = tid >> 6;
-  const int wm = wave / WAVES_N;
-  const int wn = wave - wm * WAVES_N;
+  const int grp = wave / NWG;
+  const int wig = wave - grp * NWG;
+  const int wm = wig / WAVES_N;
+  const int wn = wig - wm * WAVES_N;
   const int ktot = (g.K * Tr::esize + SEGB - 1) / SEGB;
   const int kt0 = blockIdx.y * g.kchunk;
   const int ktiles = min(ktot - kt0, g.kchunk);   // >= 1 by construction of the split
 
-  // This wave's load instructions: global source of its lane and the LDS
-  // offset (inside a stage) of the 16-row group.
-  const unsigned char* src[IPW];
-  int dst[IPW];
+  // This wave's load instructions for one barrier interval: stage offset
+  // (0..G-1), global source of its lane, LDS offset inside a stage.
+  const unsigned char* src[IPI];
+  int dst[IPI], sof[IPI];
   {
     const int lrow = lane >> 2;
     const int chunk = (lane & 3) ^ swz(lrow);
 #pragma unroll
-    for (int i = 0; i < IPW; ++i) {
+    for (int i = 0; i < IPI; ++i) {
       const int q = wave + NW * i;
-      const int p = q / (ROWS / 16);
-      const int rg = q - p * (ROWS / 16);
+      const int gg = q / NINS;
+      const int r = q - gg * NINS;
+      const int p = r / (ROWS / 16);
+      const int rg = r - p * (ROWS / 16);
       const int row = rg * 16 + lrow;
       const unsigned char* base;
       if (row < BM)
@@ -287,17 +302,19 @@ void gemm_nt_kernel(GemmArgs g, Epi epi) {
         base = static_cast<const unsigned char*>(g.b[p]) + (long)(tn * BN + row - BM) * (g.ldb * Tr::esize);
       src[i] = base + (long)kt0 * SEGB + chunk * 16;
       dst[i] = p * PLANEB + rg * 16 * SEGB;
+      sof[i] = gg;
     }
   }
 
-#define SF_ISSUE_STAGE(KSTAGE, BUF)                                                                  \
+  // issue the G stages [J G, J G + G) into their ring buffers (indices past
+  // the end are clamped; the re-read lands in a buffer never consumed again)
+#define SF_ISSUE_GROUP(J)                                                                            \
   {                                                                                                  \
-    const long koff_ = (long)(KSTAGE) * SEGB;                                                        \
-    unsigned char* sbase_ = lds + (BUF) * STAGEB;                                                    \
-    _Pragma("unroll") for (int i_ = 0; i_ < IPW; ++i_) {                                             \
+    _Pragma("unroll") for (int i_ = 0; i_ < IPI; ++i_) {                                             \
+      const int st_ = (J) * G + sof[i_];                                                             \
       __builtin_amdgcn_global_load_lds(                                                              \
-          (const void __attribute__((address_space(1)))*)(src[i_] + koff_),                          \
-          (void __attribute__((address_space(3)))*)(sbase_ + dst[i_]), 16, 0, 0);                    \
+          (const void __attribute__((address_space(1)))*)(src[i_] + (long)min(st_, ktiles - 1) * SEGB), \
+          (void __attribute__((address_space(3)))*)(lds + (st_ % NS) * STAGEB + dst[i_]), 16, 0, 0); \
     }                                                                                                \
   }
 
@@ -314,48 +331,95 @@ void gemm_nt_kernel(GemmArgs g, Epi epi) {
   const int a_off = (wm * WM + frow) * SEGB + fchunk;
   const int b_off = (BM + wn * WN + frow) * SEGB + fchunk;
 
-  // Stages are consumed G at a time per barrier: iteration `it` computes
-  // stages [it G, it G + G).  Loads run NS - G stages ahead of the first
-  // stage consumed; at the top of an iteration NS - 2G stages may remain in
-  // flight.  Stage indices past the end are clamped (the re-read lands in a
-  // buffer that is never consumed again).
+  // Loads run NS - G stages ahead of the first stage consumed; at the top of
+  // an interval NS - 2G stages may remain in flight.
+  constexpr int AHEAD = (NS - G) / G;
 #pragma unroll
-  for (int st = 0; st < NS - G; ++st) SF_ISSUE_STAGE(min(st, ktiles - 1), st);
+  for (int j = 0; j < AHEAD; ++j) SF_ISSUE_GROUP(j);
 
   const int iters = (ktiles + G - 1) / G;
   for (int it = 0; it < iters; ++it) {
-    __builtin_amdgcn_s_waitcnt(vmcnt_imm<(NS - 2 * G) * IPW>());
+    __builtin_amdgcn_s_waitcnt(vmcnt_imm<(AHEAD - 1) * IPI>());
     __builtin_amdgcn_s_barrier();
     asm volatile("" ::: "memory");
-#pragma unroll
-    for (int gg = 0; gg < G; ++gg) {
-      const int kst = it * G + gg + NS - G;
-      SF_ISSUE_STAGE(min(kst, ktiles - 1), kst % NS);
-    }
-#pragma unroll
-    for (int gg = 0; gg < G; ++gg) {
-      const int kt = it * G + gg;
-      if (G > 1 && kt >= ktiles) break;
-      const unsigned char* sbase = lds + (kt % NS) * STAGEB;
+    if constexpr (AHEAD == 1 && G == 1 && KG == 1) {
+      // One stage in flight at a time: the stage is read with ordinary LDS
+      // loads (the compiler then overlaps them with the MFMAs through
+      // partial lgkmcnt waits) and the next stage is requested after the
+      // reads, so the compiler's own wait on the request falls at the next
+      // interval's first read, where the pipeline has to wait anyway.
+      const unsigned char* sbase = lds + (it % NS) * STAGEB;
       uint4 fa[FM][P], fb[FN][P];
-      {
-        unsigned ra[P], rb[P];
 #pragma unroll
-        for (int p = 0; p < P; ++p) {
-          ra[p] = lds_addr(sbase + p * PLANEB + a_off);
-          rb[p] = lds_addr(sbase + p * PLANEB + b_off);
-        }
-        FragLoad<P, FM, FN>::run(fa, fb, ra, rb);
+      for (int p = 0; p < P; ++p) {
+#pragma unroll
+        for (int i = 0; i < FM; ++i)
+          fa[i][p] = *reinterpret_cast<const uint4*>(sbase + p * PLANEB + a_off + i * 16 * SEGB);
+#pragma unroll
+        for (int j = 0; j < FN; ++j)
+          fb[j][p] = *reinterpret_cast<const uint4*>(sbase + p * PLANEB + b_off + j * 16 * SEGB);
       }
+      SF_ISSUE_GROUP(it + AHEAD);
 #pragma unroll
       for (int i = 0; i < FM; ++i)
 #pragma unroll
         for (int j = 0; j < FN; ++j) mma_chunk<MODE>(acc[i][j], fa[i], fb[j]);
+    } else {
+      SF_ISSUE_GROUP(it + AHEAD);
+#pragma unroll
+      for (int gg = 0; gg < G; ++gg) {
+        if (KG > 1 && (gg % KG) != grp) continue;
+        const int kt = it * G + gg;
+        if (G > 1 && kt >= ktiles) break;
+        const unsigned char* sbase = lds + (kt % NS) * STAGEB;
+        uint4 fa[FM][P], fb[FN][P];
+        {
+          unsigned ra[P], rb[P];
+#pragma unroll
+          for (int p = 0; p < P; ++p) {
+            ra[p] = lds_addr(sbase + p * PLANEB + a_off);
+            rb[p] = lds_addr(sbase + p * PLANEB + b_off);
+          }
+          FragLoad<P, FM, FN>::run(fa, fb, ra, rb);
+        }
+#pragma unroll
+        for (int i = 0; i < FM; ++i)
+#pragma unroll
+          for (int j = 0; j < FN; ++j) mma_chunk<MODE>(acc[i][j], fa[i], fb[j]);
+      }
     }
     asm volatile("" ::: "memory");
   }
   __builtin_amdgcn_s_waitcnt(vmcnt_imm<0>());
-#undef SF_ISSUE_STAGE
+#undef SF_ISSUE_GROUP
+
+  if constexpr (KG > 1) {
+    // groups 1.. hand their partial sums to group 0 through LDS (fixed order)
+    Acc* red = reinterpret_cast<Acc*>(lds);
+    __builtin_amdgcn_s_barrier();
+    asm volatile("" ::: "memory");
+    for (int q = 1; q < KG; ++q) {
+      if (grp == q) {
+#pragma unroll
+        for (int i = 0; i < FM; ++i)
+#pragma unroll
+          for (int j = 0; j < FN; ++j)
+#pragma unroll
+            for (int t = 0; t < 4; ++t) red[(((wig * FM + i) * FN + j) * 4 + t) * 64 + lane] = acc[i][j][t];
+      }
+      __syncthreads();
+      if (grp == 0) {
+#pragma unroll
+        for (int i = 0; i < FM; ++i)
+#pragma unroll
+          for (int j = 0; j < FN; ++j)
+#pragma unroll
+            for (int t = 0; t < 4; ++t) acc[i][j][t] += red[(((wig * FM + i) * FN + j) * 4 + t) * 64 + lane];
+      }
+      __syncthreads();
+    }
+    if (grp != 0) return;
+  }
 
   // epilogue
   constexpr int RSTEP = (MODE == M_F64) ? 4 : 1;          // row stride between accumulator registers
@@ -385,10 +449,14 @@ void gemm_nt_kernel(GemmArgs g, Epi epi) {
 #ifndef SF_TILE_G
 #define SF_TILE_G 1
 #endif
+#ifndef SF_TILE_KG
+#define SF_TILE_KG 1
+#endif
 struct TileCfg {
   static constexpr int BM = SF_TILE_BM, BN = SF_TILE_BN, WM = SF_TILE_WM, WN = SF_TILE_WN;
   static constexpr int NS = SF_TILE_NS;   // LDS pipeline stages of 64 K-bytes
   static constexpr int G = SF_TILE_G;     // stages consumed per barrier
+  static constexpr int KG = SF_TILE_KG;   // K groups of waves inside a workgroup
   static constexpr int ROW_PAD = 256;     // operand row allocations are multiples of this
   static constexpr int K_PAD = 64;        // operand leading dimensions are multiples of this
   static_assert(BM <= ROW_PAD && BN <= ROW_PAD, "row padding must cover a tile");
@@ -396,7 +464,9 @@ struct TileCfg {
 
 template <int MODE>
 constexpr size_t gemm_lds_bytes() {
-  return (size_t)TileCfg::NS * ModeTraits<MODE>::planes * (TileCfg::BM + TileCfg::BN) * 64;
+  const size_t stages = (size_t)TileCfg::NS * ModeTraits<MODE>::planes * (TileCfg::BM + TileCfg::BN) * 64;
+  const size_t red = TileCfg::KG > 1 ? (size_t)TileCfg::BM * TileCfg::BN * sizeof(typename ModeTraits<MODE>::Acc) : 0;
+  return stages > red ? stages : red;
 }
 
 // Partial product of one K split, stored for the reduction.
@@ -444,18 +514,18 @@ hipError_t launch_gemm(GemmArgs g, const Epi& epi, hipStream_t s, int S = 1,
   constexpr int BM = TileCfg::BM, BN = TileCfg::BN, WM = TileCfg::WM, WN = TileCfg::WN;
   if (g.M <= 0 || g.N <= 0) return hipSuccess;
   const int tiles = ((g.M + BM - 1) / BM) * ((g.N + BN - 1) / BN);
-  constexpr int threads = (BM / WM) * (BN / WN) * 64;
+  constexpr int threads = TileCfg::KG * (BM / WM) * (BN / WN) * 64;
   const int kst = gemm_kstages<MODE>(g.K);
   if (S <= 1 || !ws) {
     g.kchunk = kst;
-    hipLaunchKernelGGL((gemm_nt_kernel<MODE, BM, BN, WM, WN, TileCfg::NS, TileCfg::G, Epi>), dim3(tiles),
+    hipLaunchKernelGGL((gemm_nt_kernel<MODE, BM, BN, WM, WN, TileCfg::NS, TileCfg::G, TileCfg::KG, Epi>), dim3(tiles),
                        dim3(threads), 0, s, g, epi);
     return hipGetLastError();
   }
   g.kchunk = (kst + S - 1) / S;
   S = (kst + g.kchunk - 1) / g.kchunk;   // every split non-empty
   EpiPartial<MODE> part{ws, g.M, g.N};
-  hipLaunchKernelGGL((gemm_nt_kernel<MODE, BM, BN, WM, WN, TileCfg::NS, TileCfg::G, EpiPartial<MODE>>),
+  hipLaunchKernelGGL((gemm_nt_kernel<MODE, BM, BN, WM, WN, TileCfg::NS, TileCfg::G, TileCfg::KG, EpiPartial<MODE>>),
                      dim3(tiles, S), dim3(threads), 0, s, g, part);
   hipLaunchKernelGGL((splitk_reduce_kernel<typename ModeTraits<MODE>::Acc, Epi>), dim3(2048), dim3(256), 0, s,
                      ws, S, g.M, g.N, epi);
