@@ -27,6 +27,24 @@ __device__ __forceinline__ uint16_t f32_to_f16(float f) {
   return __builtin_bit_cast(uint16_t, static_cast<_Float16>(f));
 }
 
+// GEMM operand layout in device memory.  An operand is a (rows x ld) matrix
+// whose K index runs along ld (a multiple of 64 elements).  It is stored in
+// blocks of 16 rows x 64 bytes of K (1 KB); blocks run along K first, then
+// down the rows.  Inside a block the layout is chunk-major: the 16-byte
+// chunk g (K bytes [16 g, 16 g + 16)) of row r sits at byte 16 (16 g + r).
+// A block is then exactly what one MFMA fragment load wants (lane l holds row
+// l % 16, chunk l / 16 at byte 16 l), and the GEMM moves it from memory to
+// LDS with one contiguous 1 KB transfer per wave.
+template <int MODE>
+__device__ __forceinline__ long op_index(long row, long k, long ld) {
+  constexpr int ES = ModeTraits<MODE>::esize;
+  constexpr int KSEG = 64 / ES;   // K elements per block
+  constexpr int CE = 16 / ES;     // K elements per chunk
+  const long blk = (row >> 4) * (ld / KSEG) + k / KSEG;
+  const int kin = (int)(k % KSEG);
+  return blk * (1024 / ES) + ((kin / CE) * 16 + (row & 15)) * CE + (kin % CE);
+}
+
 // Store one value into the operand planes of a GEMM mode.  BF16X3 keeps
 // v = hi + lo with hi = bf16(v), lo = bf16(v - hi); `vlo` carries the low
 // word of a float-float value when there is one.

@@ -1,8 +1,9 @@
 // Term-stacked "NT" GEMM on gfx950 MFMA:  C[M x N] = A[M x K] * B[N x K]^T.
 //
-// Both operands are row-major with K contiguous, so every GEMM of the sFISTA
-// iteration reads 16-byte chunks along K from LDS for both operands.  The
-// caller guarantees the padding contract:
+// Both operands are stored in the blocked K-major operand layout of
+// op_index (common.hpp), so every GEMM of the sFISTA iteration streams whole
+// 1 KB blocks (16 rows x 64 K-bytes) into LDS.  The caller guarantees the
+// padding contract:
 //   * A has at least round_up(M, BM) rows and B at least round_up(N, BN) rows;
 //   * lda, ldb >= round_up(K, 64 elements) and the entries in [K, lda) are 0,
 // so the main loop needs no bounds checks; only the epilogue masks rows >= M
@@ -210,8 +211,6 @@ __device__ __forceinline__ unsigned lds_addr(const void* p) {
   return static_cast<unsigned>(reinterpret_cast<uintptr_t>((const __attribute__((address_space(3))) void*)p));
 }
 
-__device__ __forceinline__ int swz(int r) { return ((r >> 1) ^ (r >> 3)) & 3; }
-
 // s_waitcnt immediate that waits until at most N vector-memory operations
 // are outstanding (expcnt and lgkmcnt left at their no-wait maxima).
 template <int N>
@@ -221,15 +220,15 @@ constexpr int vmcnt_imm() {
 }
 
 // LDS staging: NS stages, each holding 64 bytes of K for the BM + BN rows of
-// every plane.  Rows are 64 bytes apart with no padding; the four 16-byte
-// chunks of row r are XOR-swizzled: chunk c lives at c ^ f(r & 15) with
-// f(r) = ((r >> 1) ^ (r >> 3)) & 3.  The 16 rows read by one fragment load
-// then land on 16 distinct 16-byte slots of a 256-byte bank window, and each
-// half of them on 8 distinct slots of a 128-byte window.
+// every plane, as the 1 KB blocks of the operand layout (op_index: 16 rows x
+// 64 K-bytes, chunk-major inside).  An MFMA fragment wants lane l to hold row
+// l % 16, chunk l / 16, i.e. byte 16 l of a block, so every fragment read is
+// one contiguous 1 KB wave access, the pattern the LDS serves at full rate
+// (16-row gathers from a row-major tile run at half rate on gfx950, with or
+// without padding or XOR swizzles).
 //
-// Global -> LDS uses gfx950's global_load_lds_dwordx4: one instruction moves
-// 16 rows x 64 bytes (lane L writes LDS bytes [16 L, 16 L + 16)), with lane L
-// fetching the logical chunk that the swizzle places at its slot.  Loads run
+// Global -> LDS uses gfx950's global_load_lds_dwordx4: one instruction copies
+// one contiguous 1 KB block (lane L moves bytes [16 L, 16 L + 16)).  Loads run
 // NS - 1 stages ahead; each stage starts with a wait until the wave's loads of
 // that stage have landed and a workgroup barrier that publishes all waves'
 // loads (and retires every wave's reads of the stage about to be refilled).
@@ -285,8 +284,8 @@ void gemm_nt_kernel(GemmArgs g, Epi epi) {
   const unsigned char* src[IPI];
   int dst[IPI], sof[IPI];
   {
-    const int lrow = lane >> 2;
-    const int chunk = (lane & 3) ^ swz(lrow);
+    const long nseg_a = g.lda * Tr::esize / SEGB;   // K blocks per 16-row block of A
+    const long nseg_b = g.ldb * Tr::esize / SEGB;
 #pragma unroll
     for (int i = 0; i < IPI; ++i) {
       const int q = wave + NW * i;
@@ -294,13 +293,13 @@ void gemm_nt_kernel(GemmArgs g, Epi epi) {
       const int r = q - gg * NINS;
       const int p = r / (ROWS / 16);
       const int rg = r - p * (ROWS / 16);
-      const int row = rg * 16 + lrow;
       const unsigned char* base;
-      if (row < BM)
-        base = static_cast<const unsigned char*>(g.a[p]) + (long)(tm * BM + row) * (g.lda * Tr::esize);
+      if (rg < BM / 16)
+        base = static_cast<const unsigned char*>(g.a[p]) + ((long)(tm * (BM / 16) + rg) * nseg_a + kt0) * 1024;
       else
-        base = static_cast<const unsigned char*>(g.b[p]) + (long)(tn * BN + row - BM) * (g.ldb * Tr::esize);
-      src[i] = base + (long)kt0 * SEGB + chunk * 16;
+        base = static_cast<const unsigned char*>(g.b[p]) +
+               ((long)(tn * (BN / 16) + rg - BM / 16) * nseg_b + kt0) * 1024;
+      src[i] = base + lane * 16;
       dst[i] = p * PLANEB + rg * 16 * SEGB;
       sof[i] = gg;
     }
@@ -313,7 +312,7 @@ void gemm_nt_kernel(GemmArgs g, Epi epi) {
     _Pragma("unroll") for (int i_ = 0; i_ < IPI; ++i_) {                                             \
       const int st_ = (J) * G + sof[i_];                                                             \
       __builtin_amdgcn_global_load_lds(                                                              \
-          (const void __attribute__((address_space(1)))*)(src[i_] + (long)min(st_, ktiles - 1) * SEGB), \
+          (const void __attribute__((address_space(1)))*)(src[i_] + (long)min(st_, ktiles - 1) * 1024), \
           (void __attribute__((address_space(3)))*)(lds + (st_ % NS) * STAGEB + dst[i_]), 16, 0, 0); \
     }                                                                                                \
   }
@@ -324,12 +323,9 @@ void gemm_nt_kernel(GemmArgs g, Epi epi) {
 #pragma unroll
     for (int j = 0; j < FN; ++j) acc[i][j] = AccT{0, 0, 0, 0};
 
-  // fragment reads: lane reads logical chunk (lane >> 4) of row (lane & 15)
-  // of each 16-row block; the swizzle term depends only on (lane & 15).
-  const int frow = lane & 15;
-  const int fchunk = ((lane >> 4) ^ swz(frow)) * 16;
-  const int a_off = (wm * WM + frow) * SEGB + fchunk;
-  const int b_off = (BM + wn * WN + frow) * SEGB + fchunk;
+  // fragment reads: 16-row block i of this wave's rows, byte 16 lane of it
+  const int a_off = wm * WM * SEGB + lane * 16;
+  const int b_off = (BM + wn * WN) * SEGB + lane * 16;
 
   // Loads run NS - G stages ahead of the first stage consumed; at the top of
   // an interval NS - 2G stages may remain in flight.

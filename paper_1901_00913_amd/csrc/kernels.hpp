@@ -104,7 +104,7 @@ __global__ void init_state_kernel(const double* x0, void* st0, void* st1, int ki
     state_set(st0, kind, e, v);
     state_set(st1, kind, e, v);
     const long i = e / n, j = e - i * n;
-    store_planes<MODE>(y, i * ldy + j, v);
+    store_planes<MODE>(y, op_index<MODE>(i, j, ldy), v);
   }
 }
 
@@ -117,7 +117,7 @@ __global__ void to_planes_kernel(const double* x, const double* sumsq, void* p0,
   const long total = (long)m * n;
   for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < total; e += (long)gridDim.x * blockDim.x) {
     const long i = e / n, j = e - i * n;
-    store_planes<MODE>(p, i * ldp + j, x[e] * scale);
+    store_planes<MODE>(p, op_index<MODE>(i, j, ldp), x[e] * scale);
   }
 }
 
@@ -130,9 +130,9 @@ __global__ void state_to_planes_kernel(const void* st, int kind, void* p0, void*
     const long i = e / n, j = e - i * n;
     if (kind == ST_PAIR) {
       const float2 v = static_cast<const float2*>(st)[e];
-      store_planes<MODE>(p, i * ldp + j, static_cast<double>(v.x), v.y);
+      store_planes<MODE>(p, op_index<MODE>(i, j, ldp), static_cast<double>(v.x), v.y);
     } else {
-      store_planes<MODE>(p, i * ldp + j, state_get(st, kind, e));
+      store_planes<MODE>(p, op_index<MODE>(i, j, ldp), state_get(st, kind, e));
     }
   }
 }
@@ -187,13 +187,13 @@ __global__ void pack_kernel(const double* __restrict__ src, void* o0, void* o1, 
       const long k = col / d, b = col - k * d;
       s = (k * d + b) * d + row;
     }
-    store_planes<MODE>(o, row * ldo + col, src[s]);
+    store_planes<MODE>(o, op_index<MODE>(row, col, ldo), src[s]);
   }
 }
 
 // ------------------------------------------------------------- epilogues
 // F1 / G1: output row p = (k, a) of a term-stacked GEMM goes to row a and
-// column block k of the next operand: out[a * ldo + k * colblk + col].
+// column block k of the next operand: element (a, k * colblk + col).
 template <int MODE>
 struct EpiStack {
   void* out[2];
@@ -202,7 +202,7 @@ struct EpiStack {
   __device__ __forceinline__ void operator()(int row, int col, typename ModeTraits<MODE>::Acc v) const {
     const int k = row / D;
     const int a = row - k * D;
-    const long idx = (long)a * ldo + (long)k * colblk + col;
+    const long idx = op_index<MODE>(a, (long)k * colblk + col, ldo);
     if constexpr (MODE == M_F64) store_planes<MODE>(out, idx, v);
     else store_planes_f<MODE>(out, idx, v);
   }
@@ -221,7 +221,7 @@ struct EpiResid {
   int n;
   __device__ __forceinline__ void operator()(int j, int i, Acc v) const {
     const Acc r = bobs_t ? v - bobs_t[(long)j * m + i] : v;
-    const long idx = (long)j * ldo + i;
+    const long idx = op_index<MODE>(j, i, ldo);
     if constexpr (MODE == M_F64) store_planes<MODE>(out, idx, r);
     else store_planes_f<MODE>(out, idx, r);
     if (copy) copy[(long)i * n + j] = static_cast<double>(r);
@@ -257,7 +257,7 @@ struct EpiUpdate {
   int nonneg;
   __device__ __forceinline__ void operator()(int i, int j, Acc g) const {
     const long s = (long)i * n + j;
-    const long o = (long)i * ldy + j;
+    const long o = op_index<MODE>(i, j, ldy);
     if constexpr (KIND == ST_F64) {
       const double a1 = static_cast<const double*>(x1)[s];
       const double a2 = static_cast<double*>(x2)[s];
