@@ -32,6 +32,7 @@
 
 namespace sf {
 
+
 typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
 typedef _Float16 f16x8_t __attribute__((ext_vector_type(8)));
 typedef float f32x4_t __attribute__((ext_vector_type(4)));
@@ -338,51 +339,27 @@ void gemm_nt_kernel(GemmArgs g, Epi epi) {
     __builtin_amdgcn_s_waitcnt(vmcnt_imm<(AHEAD - 1) * IPI>());
     __builtin_amdgcn_s_barrier();
     asm volatile("" ::: "memory");
-    if constexpr (AHEAD == 1 && G == 1 && KG == 1) {
-      // One stage in flight at a time: the stage is read with ordinary LDS
-      // loads (the compiler then overlaps them with the MFMAs through
-      // partial lgkmcnt waits) and the next stage is requested after the
-      // reads, so the compiler's own wait on the request falls at the next
-      // interval's first read, where the pipeline has to wait anyway.
-      const unsigned char* sbase = lds + (it % NS) * STAGEB;
+    SF_ISSUE_GROUP(it + AHEAD);
+#pragma unroll
+    for (int gg = 0; gg < G; ++gg) {
+      if (KG > 1 && (gg % KG) != grp) continue;
+      const int kt = it * G + gg;
+      if (G > 1 && kt >= ktiles) break;
+      const unsigned char* sbase = lds + (kt % NS) * STAGEB;
       uint4 fa[FM][P], fb[FN][P];
+      {
+        unsigned ra[P], rb[P];
 #pragma unroll
-      for (int p = 0; p < P; ++p) {
-#pragma unroll
-        for (int i = 0; i < FM; ++i)
-          fa[i][p] = *reinterpret_cast<const uint4*>(sbase + p * PLANEB + a_off + i * 16 * SEGB);
-#pragma unroll
-        for (int j = 0; j < FN; ++j)
-          fb[j][p] = *reinterpret_cast<const uint4*>(sbase + p * PLANEB + b_off + j * 16 * SEGB);
+        for (int p = 0; p < P; ++p) {
+          ra[p] = lds_addr(sbase + p * PLANEB + a_off);
+          rb[p] = lds_addr(sbase + p * PLANEB + b_off);
+        }
+        FragLoad<P, FM, FN>::run(fa, fb, ra, rb);
       }
-      SF_ISSUE_GROUP(it + AHEAD);
 #pragma unroll
       for (int i = 0; i < FM; ++i)
 #pragma unroll
         for (int j = 0; j < FN; ++j) mma_chunk<MODE>(acc[i][j], fa[i], fb[j]);
-    } else {
-      SF_ISSUE_GROUP(it + AHEAD);
-#pragma unroll
-      for (int gg = 0; gg < G; ++gg) {
-        if (KG > 1 && (gg % KG) != grp) continue;
-        const int kt = it * G + gg;
-        if (G > 1 && kt >= ktiles) break;
-        const unsigned char* sbase = lds + (kt % NS) * STAGEB;
-        uint4 fa[FM][P], fb[FN][P];
-        {
-          unsigned ra[P], rb[P];
-#pragma unroll
-          for (int p = 0; p < P; ++p) {
-            ra[p] = lds_addr(sbase + p * PLANEB + a_off);
-            rb[p] = lds_addr(sbase + p * PLANEB + b_off);
-          }
-          FragLoad<P, FM, FN>::run(fa, fb, ra, rb);
-        }
-#pragma unroll
-        for (int i = 0; i < FM; ++i)
-#pragma unroll
-          for (int j = 0; j < FN; ++j) mma_chunk<MODE>(acc[i][j], fa[i], fb[j]);
-      }
     }
     asm volatile("" ::: "memory");
   }
