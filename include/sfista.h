@@ -150,6 +150,52 @@ int sfista_apply(sfista_handle h, const double* X, double* AX, double* AtAX);
 int sfista_set_timing(sfista_handle h, int enable);
 int sfista_kernel_times(sfista_handle h, double* avg_ms, long* launches);
 
+/* ------------------------------------------------------------------------
+ * Batched form: many independent problems of Algorithm 2 (each with its own
+ * image size, factors, rank, lambda and L) advanced together.  Each of the
+ * four products of an iteration is one grouped launch over the tiles of all
+ * problems; the momentum weights come from a device table indexed by a device
+ * iteration counter, so a chunk of iterations can be captured once as a HIP
+ * graph and replayed.  The batch runs on an internal stream of its own.
+ * ------------------------------------------------------------------------ */
+typedef struct {
+    const double* Bobs;  /* (device) m x n observed image */
+    int m, n;            /* image size */
+    const double* A;     /* (device) r x n x n right factors */
+    const double* B;     /* (device) r x m x m left factors */
+    int r;               /* Kronecker terms */
+    double lambda;       /* Tikhonov parameter, finite and >= 0 */
+    double L;            /* Lipschitz constant; <= 0 runs the power iteration */
+} sfista_batch_item;
+
+typedef struct sfista_batch* sfista_batch_handle;
+
+#define SFISTA_BATCH_AUTOTUNE 1  /* time the candidate tile shapes of each product at setup */
+#define SFISTA_BATCH_GRAPH 2     /* replay chunks of 10 iterations from a captured HIP graph */
+
+/* Build a batch of `count` problems.  `common` (host) supplies precision,
+ * nonneg, power_iters and pair_state for all of them (its lambda, L, x0, v0
+ * are ignored; every problem starts from X_0 = 0).  `max_iters` bounds the
+ * iterations the batch may run (the size of its momentum table).  `flags`
+ * is a mask of SFISTA_BATCH_*.  With SFISTA_BATCH_AUTOTUNE the choice of tile
+ * shape per product is cached in the file named by the environment variable
+ * SFISTA_TUNE_CACHE when it is set.  Inputs may be freed after the call. */
+int sfista_batch_setup(const sfista_batch_item* items, int count, const sfista_params* common, int max_iters,
+                       int flags, hipStream_t stream, sfista_batch_handle* out);
+
+/* Run `iters` more iterations of every problem, then write the reports.
+ *   X_out (host array of `count` device pointers, nullable; entries nullable)
+ *         receives each problem's m x n FP64 iterate.
+ *   reps  (host, `count` entries, nullable).
+ * Synchronous. */
+int sfista_batch_solve(sfista_batch_handle h, int iters, double* const* X_out, sfista_report* reps);
+
+/* Tile shape chosen per product (host, 4 entries: F1, F2, G1, G2); 0 = 128 x 128
+ * tiles of 8 waves, 1 = 64 x 64 tiles of 4 waves. */
+int sfista_batch_tiles(sfista_batch_handle h, int* choice);
+
+void sfista_batch_destroy(sfista_batch_handle h);
+
 /* Lipschitz constant in use by the plan (estimated or given). */
 int sfista_get_L(sfista_handle h, double* L);
 

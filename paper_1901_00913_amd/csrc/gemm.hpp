@@ -240,12 +240,13 @@ constexpr int vmcnt_imm() {
 // accumulators through LDS and group 0 runs the epilogue.  KG = 2 lets eight
 // waves share a 128 x 128 tile with 64 x 64 sub-tiles, which halves the LDS
 // fragment traffic per MFMA compared with 64 x 32 sub-tiles.
-template <int MODE, int BM, int BN, int WM, int WN, int NS, int G, int KG, class Epi>
-__global__ __launch_bounds__(KG * (BM / WM) * (BN / WN) * 64, 1)
-void gemm_nt_kernel(GemmArgs g, Epi epi) {
+template <int MODE, class T, class Epi>
+__device__ __forceinline__ void gemm_tile(unsigned char* lds, const GemmArgs& g, int tm, int tn, int kz,
+                                          const Epi& epi) {
   using Tr = ModeTraits<MODE>;
   using AccT = typename AccVec<MODE>::T;
   using Acc = typename Tr::Acc;
+  constexpr int BM = T::BM, BN = T::BN, WM = T::WM, WN = T::WN, NS = T::NS, G = T::G, KG = T::KG;
   constexpr int P = Tr::planes;
   constexpr int WAVES_N = BN / WN;
   constexpr int NWG = (BM / WM) * WAVES_N;    // waves per K group
@@ -257,17 +258,8 @@ void gemm_nt_kernel(GemmArgs g, Epi epi) {
   constexpr int NINS = P * ROWS / 16;         // 16-row load instructions per stage
   constexpr int IPI = G * NINS / NW;          // load instructions per wave per barrier interval
   constexpr int FM = WM / 16, FN = WN / 16;
-  constexpr int REDB = KG > 1 ? NWG * FM * FN * 4 * 64 * (int)sizeof(Acc) : 0;
-  constexpr int LDSB = NS * STAGEB > REDB ? NS * STAGEB : REDB;
   static_assert((G * NINS) % NW == 0 && BM % 16 == 0 && BN % 16 == 0, "tile/waves");
   static_assert(G >= 1 && NS >= 2 * G && NS % G == 0 && G % KG == 0, "stages per barrier");
-
-  __shared__ __attribute__((aligned(16))) unsigned char lds[LDSB];
-
-  const int tiles_m = (g.M + BM - 1) / BM;
-  const int tiles_n = (g.N + BN - 1) / BN;
-  int tm, tn;
-  map_tile(blockIdx.x, gridDim.x, tiles_m, tiles_n, tm, tn);
 
   const int tid = threadIdx.x;
   const int lane = tid & 63;
@@ -277,7 +269,7 @@ void gemm_nt_kernel(GemmArgs g, Epi epi) {
   const int wm = wig / WAVES_N;
   const int wn = wig - wm * WAVES_N;
   const int ktot = (g.K * Tr::esize + SEGB - 1) / SEGB;
-  const int kt0 = blockIdx.y * g.kchunk;
+  const int kt0 = kz * g.kchunk;
   const int ktiles = min(ktot - kt0, g.kchunk);   // >= 1 by construction of the split
 
   // This wave's load instructions for one barrier interval: stage offset
@@ -411,7 +403,9 @@ void gemm_nt_kernel(GemmArgs g, Epi epi) {
     }
 }
 
-// Tile configuration of the single kernel family.
+// Tile configurations.  TileL (128 x 128, 8 waves of 64 x 32, two 64 KB
+// LDS stages for bf16x3) is the single-image shape; TileS (64 x 64, 4 waves
+// of 32 x 32) serves small images in the batched form.
 #ifndef SF_TILE_BM
 #define SF_TILE_BM 128
 #define SF_TILE_BN 128
@@ -425,21 +419,61 @@ void gemm_nt_kernel(GemmArgs g, Epi epi) {
 #ifndef SF_TILE_KG
 #define SF_TILE_KG 1
 #endif
+template <int BM_, int BN_, int WM_, int WN_, int NS_, int G_, int KG_>
+struct Tile {
+  static constexpr int BM = BM_, BN = BN_, WM = WM_, WN = WN_;
+  static constexpr int NS = NS_;   // LDS pipeline stages of 64 K-bytes
+  static constexpr int G = G_;     // stages consumed per barrier
+  static constexpr int KG = KG_;   // K groups of waves inside a workgroup
+  static constexpr int THREADS = KG * (BM / WM) * (BN / WN) * 64;
+  template <int MODE>
+  static constexpr int lds_bytes() {
+    using Acc = typename ModeTraits<MODE>::Acc;
+    constexpr int stages = NS * ModeTraits<MODE>::planes * (BM + BN) * 64;
+    constexpr int red = KG > 1 ? BM * BN * (int)sizeof(Acc) : 0;
+    return stages > red ? stages : red;
+  }
+};
+using TileL = Tile<SF_TILE_BM, SF_TILE_BN, SF_TILE_WM, SF_TILE_WN, SF_TILE_NS, SF_TILE_G, SF_TILE_KG>;
+using TileS = Tile<64, 64, 32, 32, 4, 1, 1>;
+
 struct TileCfg {
-  static constexpr int BM = SF_TILE_BM, BN = SF_TILE_BN, WM = SF_TILE_WM, WN = SF_TILE_WN;
-  static constexpr int NS = SF_TILE_NS;   // LDS pipeline stages of 64 K-bytes
-  static constexpr int G = SF_TILE_G;     // stages consumed per barrier
-  static constexpr int KG = SF_TILE_KG;   // K groups of waves inside a workgroup
   static constexpr int ROW_PAD = 256;     // operand row allocations are multiples of this
   static constexpr int K_PAD = 64;        // operand leading dimensions are multiples of this
-  static_assert(BM <= ROW_PAD && BN <= ROW_PAD, "row padding must cover a tile");
+  static_assert(TileL::BM <= ROW_PAD && TileL::BN <= ROW_PAD, "row padding must cover a tile");
 };
 
-template <int MODE>
-constexpr size_t gemm_lds_bytes() {
-  const size_t stages = (size_t)TileCfg::NS * ModeTraits<MODE>::planes * (TileCfg::BM + TileCfg::BN) * 64;
-  const size_t red = TileCfg::KG > 1 ? (size_t)TileCfg::BM * TileCfg::BN * sizeof(typename ModeTraits<MODE>::Acc) : 0;
-  return stages > red ? stages : red;
+template <int MODE, class T = TileL>
+constexpr size_t gemm_lds_bytes() { return (size_t)T::template lds_bytes<MODE>(); }
+
+template <int MODE, class T, class Epi>
+__global__ __launch_bounds__(T::THREADS, 1) void gemm_nt_kernel(GemmArgs g, Epi epi) {
+  __shared__ __attribute__((aligned(16))) unsigned char lds[T::template lds_bytes<MODE>()];
+  const int tiles_m = (g.M + T::BM - 1) / T::BM;
+  const int tiles_n = (g.N + T::BN - 1) / T::BN;
+  int tm, tn;
+  map_tile(blockIdx.x, gridDim.x, tiles_m, tiles_n, tm, tn);
+  gemm_tile<MODE, T>(lds, g, tm, tn, blockIdx.y, epi);
+}
+
+// One tile of one product of a batch: the product index selects the GEMM
+// arguments and the epilogue parameters.
+struct WorkItem {
+  int prod, tm, tn, pad;
+};
+
+// Grouped launch: every workgroup computes the tile of the batch's work list
+// that its (XCD-grouped) id names.
+template <int MODE, class T, class Epi>
+__global__ __launch_bounds__(T::THREADS, 1) void gemm_grouped_kernel(const GemmArgs* args, const Epi* epis,
+                                                                     const WorkItem* work) {
+  __shared__ __attribute__((aligned(16))) unsigned char lds[T::template lds_bytes<MODE>()];
+  int bid = blockIdx.x;
+  if ((gridDim.x & 7) == 0) bid = (bid & 7) * (gridDim.x >> 3) + (bid >> 3);
+  const WorkItem w = work[bid];
+  const GemmArgs g = args[w.prod];
+  const Epi e = epis[w.prod];
+  gemm_tile<MODE, T>(lds, g, w.tm, w.tn, 0, e);
 }
 
 // Partial product of one K split, stored for the reduction.
@@ -472,7 +506,7 @@ inline int gemm_kstages(int K) { return (K * ModeTraits<MODE>::esize + 63) / 64;
 // `slots` (CUs x resident blocks per CU), keeping at least 16 K stages per split.
 template <int MODE>
 inline int choose_splitk(int M, int N, int K, int slots) {
-  const int tiles = ((M + TileCfg::BM - 1) / TileCfg::BM) * ((N + TileCfg::BN - 1) / TileCfg::BN);
+  const int tiles = ((M + TileL::BM - 1) / TileL::BM) * ((N + TileL::BN - 1) / TileL::BN);
   const int kst = gemm_kstages<MODE>(K);
   int S = 1;
   while (S < 16 && tiles * S * 2 <= slots && kst / (S * 2) >= 16) S *= 2;
@@ -484,21 +518,21 @@ inline int choose_splitk(int M, int N, int K, int slots) {
 template <int MODE, class Epi>
 hipError_t launch_gemm(GemmArgs g, const Epi& epi, hipStream_t s, int S = 1,
                        typename ModeTraits<MODE>::Acc* ws = nullptr) {
-  constexpr int BM = TileCfg::BM, BN = TileCfg::BN, WM = TileCfg::WM, WN = TileCfg::WN;
+  using T = TileL;
   if (g.M <= 0 || g.N <= 0) return hipSuccess;
-  const int tiles = ((g.M + BM - 1) / BM) * ((g.N + BN - 1) / BN);
-  constexpr int threads = TileCfg::KG * (BM / WM) * (BN / WN) * 64;
+  const int tiles = ((g.M + T::BM - 1) / T::BM) * ((g.N + T::BN - 1) / T::BN);
+  constexpr int threads = T::THREADS;
   const int kst = gemm_kstages<MODE>(g.K);
   if (S <= 1 || !ws) {
     g.kchunk = kst;
-    hipLaunchKernelGGL((gemm_nt_kernel<MODE, BM, BN, WM, WN, TileCfg::NS, TileCfg::G, TileCfg::KG, Epi>), dim3(tiles),
+    hipLaunchKernelGGL((gemm_nt_kernel<MODE, T, Epi>), dim3(tiles),
                        dim3(threads), 0, s, g, epi);
     return hipGetLastError();
   }
   g.kchunk = (kst + S - 1) / S;
   S = (kst + g.kchunk - 1) / g.kchunk;   // every split non-empty
   EpiPartial<MODE> part{ws, g.M, g.N};
-  hipLaunchKernelGGL((gemm_nt_kernel<MODE, BM, BN, WM, WN, TileCfg::NS, TileCfg::G, TileCfg::KG, EpiPartial<MODE>>),
+  hipLaunchKernelGGL((gemm_nt_kernel<MODE, T, EpiPartial<MODE>>),
                      dim3(tiles, S), dim3(threads), 0, s, g, part);
   hipLaunchKernelGGL((splitk_reduce_kernel<typename ModeTraits<MODE>::Acc, Epi>), dim3(2048), dim3(256), 0, s,
                      ws, S, g.M, g.N, epi);

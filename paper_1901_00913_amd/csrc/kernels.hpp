@@ -238,12 +238,48 @@ struct EpiStore {
   }
 };
 
-// G2 + Steps 1 and 3 of Algorithm 2, fused:
+// Steps 1 and 3 of Algorithm 2 at one pixel, given G = sum_j B_j^T R A_j:
 //   Y_k     = X_{k-1} + beta_{k-1} (X_{k-1} - X_{k-2})
 //   X_k     = (L Y_k - G) / (L + lambda^2)          [max(0, .) if nonneg]
 //   Y_{k+1} = X_k + beta_k (X_k - X_{k-1})
-// G is the accumulator sum_j B_j^T R A_j.  X_k overwrites X_{k-2} in place.
-// The planes of Y_{k+1} feed the next iteration's F1.
+// X_k overwrites X_{k-2} in place (state index s); the planes of Y_{k+1}
+// (operand index o) feed the next iteration's F1.
+template <int MODE, int KIND>
+__device__ __forceinline__ void update_point(void* const* y, long o, const void* x1, void* x2, long s,
+                                             typename ModeTraits<MODE>::Acc g, double c1, double c2, double bp,
+                                             double bc, int nonneg) {
+  if constexpr (KIND == ST_F64) {
+    const double a1 = static_cast<const double*>(x1)[s];
+    const double a2 = static_cast<double*>(x2)[s];
+    const double yk = a1 + bp * (a1 - a2);
+    double xk = c1 * yk - c2 * static_cast<double>(g);
+    if (nonneg) xk = fmax(xk, 0.0);
+    const double yn = xk + bc * (xk - a1);
+    static_cast<double*>(x2)[s] = xk;
+    store_planes<MODE>(y, o, yn);
+  } else if constexpr (KIND == ST_PAIR) {
+    const float2 p1 = static_cast<const float2*>(x1)[s];
+    const float2 p2 = static_cast<float2*>(x2)[s];
+    const ff a1{p1.x, p1.y}, a2{p2.x, p2.y};
+    const ff yk = ff_add(a1, ff_mul(ff_from_double(bp), ff_add(a1, ff_neg(a2))));
+    ff xk = ff_add(ff_mul(ff_from_double(c1), yk), ff_neg(ff_mul_f(ff_from_double(c2), static_cast<float>(g))));
+    if (nonneg && (xk.hi < 0.f || (xk.hi == 0.f && xk.lo < 0.f))) xk = ff{0.f, 0.f};
+    const ff yn = ff_add(xk, ff_mul(ff_from_double(bc), ff_add(xk, ff_neg(a1))));
+    static_cast<float2*>(x2)[s] = make_float2(xk.hi, xk.lo);
+    store_planes_f<MODE>(y, o, yn.hi, yn.lo);
+  } else {
+    const float a1 = static_cast<const float*>(x1)[s];
+    const float a2 = static_cast<float*>(x2)[s];
+    const float yk = a1 + static_cast<float>(bp) * (a1 - a2);
+    float xk = static_cast<float>(c1) * yk - static_cast<float>(c2) * static_cast<float>(g);
+    if (nonneg) xk = fmaxf(xk, 0.f);
+    const float yn = xk + static_cast<float>(bc) * (xk - a1);
+    static_cast<float*>(x2)[s] = xk;
+    store_planes_f<MODE>(y, o, yn);
+  }
+}
+
+// G2 epilogue with the iteration's constants passed by the host.
 template <int MODE, int KIND>
 struct EpiUpdate {
   using Acc = typename ModeTraits<MODE>::Acc;
@@ -256,38 +292,35 @@ struct EpiUpdate {
   double bp, bc;    // beta_{k-1}, beta_k
   int nonneg;
   __device__ __forceinline__ void operator()(int i, int j, Acc g) const {
-    const long s = (long)i * n + j;
-    const long o = op_index<MODE>(i, j, ldy);
-    if constexpr (KIND == ST_F64) {
-      const double a1 = static_cast<const double*>(x1)[s];
-      const double a2 = static_cast<double*>(x2)[s];
-      const double yk = a1 + bp * (a1 - a2);
-      double xk = c1 * yk - c2 * static_cast<double>(g);
-      if (nonneg) xk = fmax(xk, 0.0);
-      const double yn = xk + bc * (xk - a1);
-      static_cast<double*>(x2)[s] = xk;
-      store_planes<MODE>(y, o, yn);
-    } else if constexpr (KIND == ST_PAIR) {
-      const float2 p1 = static_cast<const float2*>(x1)[s];
-      const float2 p2 = static_cast<float2*>(x2)[s];
-      const ff a1{p1.x, p1.y}, a2{p2.x, p2.y};
-      const ff yk = ff_add(a1, ff_mul(ff_from_double(bp), ff_add(a1, ff_neg(a2))));
-      ff xk = ff_add(ff_mul(ff_from_double(c1), yk), ff_neg(ff_mul_f(ff_from_double(c2), static_cast<float>(g))));
-      if (nonneg && (xk.hi < 0.f || (xk.hi == 0.f && xk.lo < 0.f))) xk = ff{0.f, 0.f};
-      const ff yn = ff_add(xk, ff_mul(ff_from_double(bc), ff_add(xk, ff_neg(a1))));
-      static_cast<float2*>(x2)[s] = make_float2(xk.hi, xk.lo);
-      store_planes_f<MODE>(y, o, yn.hi, yn.lo);
-    } else {
-      const float a1 = static_cast<const float*>(x1)[s];
-      const float a2 = static_cast<float*>(x2)[s];
-      const float yk = a1 + static_cast<float>(bp) * (a1 - a2);
-      float xk = static_cast<float>(c1) * yk - static_cast<float>(c2) * static_cast<float>(g);
-      if (nonneg) xk = fmaxf(xk, 0.f);
-      const float yn = xk + static_cast<float>(bc) * (xk - a1);
-      static_cast<float*>(x2)[s] = xk;
-      store_planes_f<MODE>(y, o, yn);
-    }
+    update_point<MODE, KIND>(y, op_index<MODE>(i, j, ldy), x1, const_cast<void*>(x2), (long)i * n + j, g, c1, c2,
+                             bp, bc, nonneg);
   }
 };
+
+// G2 epilogue that reads the iteration number k = *counter + 1 and the
+// momentum weights beta[k - 1], beta[k] from device memory, so that the same
+// launch (for instance inside a captured graph) serves every iteration.
+template <int MODE, int KIND>
+struct EpiUpdateSeq {
+  using Acc = typename ModeTraits<MODE>::Acc;
+  void* y[2];
+  long ldy;
+  void* st[2];      // the two state buffers; X_k goes to st[k & 1]
+  int n;
+  double c1, c2;
+  int nonneg;
+  const double* beta;
+  const int* counter;
+  __device__ __forceinline__ void operator()(int i, int j, Acc g) const {
+    const int k = *counter + 1;
+    update_point<MODE, KIND>(y, op_index<MODE>(i, j, ldy), st[(k - 1) & 1], st[k & 1], (long)i * n + j, g, c1, c2,
+                             beta[k - 1], beta[k], nonneg);
+  }
+};
+
+// One-thread kernel advancing the device iteration counter.
+static __global__ void advance_counter_kernel(int* counter) {
+  if (blockIdx.x == 0 && threadIdx.x == 0) counter[0] = counter[0] + 1;
+}
 
 }  // namespace sf

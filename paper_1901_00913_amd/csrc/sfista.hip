@@ -356,13 +356,11 @@ hipError_t apply_mode(sfista_plan* h, const double* X, double* AX, double* AtAX)
 }  // namespace
 
 // ====================================================================== C ABI
-extern "C" {
+namespace {
 
-int sfista_setup(const double* Bobs, int m, int n, const double* A, const double* B, int r,
-                 const sfista_params* p, hipStream_t stream, sfista_handle* out) {
-  clear_error();
-  if (!out) return set_error(SFISTA_ERR_ARG, "out handle pointer is NULL");
-  *out = nullptr;
+// Host-side checks of one problem, before any device work.
+int validate_problem(const double* Bobs, int m, int n, const double* A, const double* B, int r,
+                     const sfista_params* p) {
   if (!Bobs || !A || !B || !p) return set_error(SFISTA_ERR_ARG, "NULL input pointer");
   if (m < 1 || n < 1) return set_error(SFISTA_ERR_ARG, "image size %d x %d must be positive", m, n);
   if (r < 1 || r > (m < n ? m : n)) return set_error(SFISTA_ERR_ARG, "rank r=%d must lie in [1, min(m,n)]", r);
@@ -373,6 +371,20 @@ int sfista_setup(const double* Bobs, int m, int n, const double* A, const double
   if (p->precision < SFISTA_FP64 || p->precision > SFISTA_BF16X3)
     return set_error(SFISTA_ERR_UNSUPPORTED, "unknown precision %d", p->precision);
   if (p->power_iters < 0) return set_error(SFISTA_ERR_ARG, "power_iters must be >= 0");
+  return SFISTA_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int sfista_setup(const double* Bobs, int m, int n, const double* A, const double* B, int r,
+                 const sfista_params* p, hipStream_t stream, sfista_handle* out) {
+  clear_error();
+  if (!out) return set_error(SFISTA_ERR_ARG, "out handle pointer is NULL");
+  *out = nullptr;
+  const int rc0 = validate_problem(Bobs, m, n, A, B, r, p);
+  if (rc0 != SFISTA_OK) return rc0;
   sfista_plan* h = new (std::nothrow) sfista_plan();
   if (!h) return set_error(SFISTA_ERR_NOMEM, "host allocation failed");
   h->m = m; h->n = n; h->r = r; h->mode = p->precision; h->nonneg = p->nonneg ? 1 : 0;
@@ -504,5 +516,399 @@ void sfista_destroy(sfista_handle h) {
 }
 
 const char* sfista_last_error(void) { return last_error_slot().c_str(); }
+
+}  // extern "C"
+
+// ======================================================================
+// Batched form
+// ======================================================================
+#include <stdlib.h>
+
+#include <algorithm>
+#include <fstream>
+#include <sstream>
+#include <type_traits>
+
+struct sfista_batch {
+  int count = 0, mode = 0, kind = 0, max_iters = 0, flags = 0;
+  long iter = 0;
+  hipStream_t s = nullptr;          // internal stream (default priority)
+  std::vector<sfista_plan*> plans;
+  DeviceArena arena;
+  GemmArgs* dargs[4] = {};          // per product: device array of GEMM arguments (one per problem)
+  void* depi[4] = {};               // per product: device array of epilogues
+  WorkItem* dwork[4][2] = {};       // per product and tile shape: work list
+  int nwork[4][2] = {};
+  int choice[4] = {0, 0, 0, 0};     // 0 = TileL, 1 = TileS
+  double* beta = nullptr;           // beta[k] = (t_k - 1) / t_{k+1}, beta[0] = 0
+  int* counter = nullptr;           // iterations completed (device)
+  hipGraphExec_t gexec = nullptr;
+  hipGraph_t graph = nullptr;
+  ~sfista_batch() {
+    if (s) (void)hipStreamSynchronize(s);
+    if (gexec) (void)hipGraphExecDestroy(gexec);
+    if (graph) (void)hipGraphDestroy(graph);
+    for (sfista_plan* p : plans) delete p;
+    if (s) (void)hipStreamDestroy(s);
+  }
+};
+
+namespace {
+
+constexpr int GRAPH_ITERS = 10;
+
+template <class T>
+int tile_shape_index() { return std::is_same<T, TileS>::value ? 1 : 0; }
+
+template <int MODE, class T, class Epi>
+hipError_t launch_grouped(sfista_batch* b, int prod) {
+  const int c = tile_shape_index<T>();
+  if (b->nwork[prod][c] == 0) return hipSuccess;
+  hipLaunchKernelGGL((gemm_grouped_kernel<MODE, T, Epi>), dim3(b->nwork[prod][c]), dim3(T::THREADS), 0, b->s,
+                     b->dargs[prod], static_cast<const Epi*>(b->depi[prod]), b->dwork[prod][c]);
+  return hipGetLastError();
+}
+
+template <int MODE, class Epi>
+hipError_t launch_product(sfista_batch* b, int prod) {
+  return b->choice[prod] ? launch_grouped<MODE, TileS, Epi>(b, prod) : launch_grouped<MODE, TileL, Epi>(b, prod);
+}
+
+template <int MODE, int KIND>
+hipError_t batch_iteration_k(sfista_batch* b) {
+  hipError_t e;
+  if ((e = launch_product<MODE, EpiStack<MODE>>(b, 0)) != hipSuccess) return e;
+  if ((e = launch_product<MODE, EpiResid<MODE>>(b, 1)) != hipSuccess) return e;
+  if ((e = launch_product<MODE, EpiStack<MODE>>(b, 2)) != hipSuccess) return e;
+  if ((e = launch_product<MODE, EpiUpdateSeq<MODE, KIND>>(b, 3)) != hipSuccess) return e;
+  hipLaunchKernelGGL(advance_counter_kernel, dim3(1), dim3(64), 0, b->s, b->counter);
+  return hipGetLastError();
+}
+
+template <int MODE>
+hipError_t batch_iteration(sfista_batch* b) {
+  if (b->kind == ST_F64) return batch_iteration_k<MODE, ST_F64>(b);
+  if (b->kind == ST_PAIR) return batch_iteration_k<MODE, ST_PAIR>(b);
+  return batch_iteration_k<MODE, ST_F32>(b);
+}
+
+// Builds the per-product GEMM arguments, epilogues and work lists.
+template <int MODE>
+int batch_build(sfista_batch* b) {
+  const int cnt = b->count;
+  std::vector<GemmArgs> args[4];
+  std::vector<EpiStack<MODE>> e0(cnt), e2(cnt);
+  std::vector<EpiResid<MODE>> e1(cnt);
+  std::vector<EpiUpdateSeq<MODE, ST_F64>> u64(cnt);
+  std::vector<EpiUpdateSeq<MODE, ST_PAIR>> upr(cnt);
+  std::vector<EpiUpdateSeq<MODE, ST_F32>> u32(cnt);
+  using Acc = typename ModeTraits<MODE>::Acc;
+  for (int i = 0; i < cnt; ++i) {
+    sfista_plan* h = b->plans[i];
+    const int m = h->m, n = h->n, r = h->r;
+    GemmArgs g;
+    g = gargs<MODE>(h->W, h->ldW, h->Y, h->ldY, r * n, m, n); args[0].push_back(g);
+    g = gargs<MODE>(h->T, h->ldT, h->Bc, h->ldBc, n, m, r * m); args[1].push_back(g);
+    g = gargs<MODE>(h->Bt, h->ldBt, h->R, h->ldR, r * m, n, m); args[2].push_back(g);
+    g = gargs<MODE>(h->S, h->ldS, h->At, h->ldAt, m, n, r * n); args[3].push_back(g);
+    for (int q = 0; q < 4; ++q) args[q].back().kchunk = gemm_kstages<MODE>(args[q].back().K);
+    e0[i].out[0] = h->T[0]; e0[i].out[1] = h->T[1]; e0[i].ldo = h->ldT; e0[i].D = n; e0[i].colblk = m;
+    e1[i].out[0] = h->R[0]; e1[i].out[1] = h->R[1]; e1[i].ldo = h->ldR;
+    e1[i].bobs_t = static_cast<const Acc*>(h->bobs_t); e1[i].m = m; e1[i].copy = nullptr; e1[i].n = n;
+    e2[i].out[0] = h->S[0]; e2[i].out[1] = h->S[1]; e2[i].ldo = h->ldS; e2[i].D = m; e2[i].colblk = n;
+    const double inv = 1.0 / (h->L + h->lam * h->lam);
+    auto fill = [&](auto& u) {
+      u.y[0] = h->Y[0]; u.y[1] = h->Y[1]; u.ldy = h->ldY;
+      u.st[0] = h->st[0]; u.st[1] = h->st[1]; u.n = n;
+      u.c1 = h->L * inv; u.c2 = inv; u.nonneg = h->nonneg; u.beta = b->beta; u.counter = b->counter;
+    };
+    fill(u64[i]); fill(upr[i]); fill(u32[i]);
+  }
+  auto upload = [&](const void* src, size_t bytes) -> void* {
+    void* d = b->arena.alloc_zero(bytes, b->s);
+    if (d && hipMemcpyAsync(d, src, bytes, hipMemcpyHostToDevice, b->s) != hipSuccess) return nullptr;
+    return d;
+  };
+  for (int q = 0; q < 4; ++q) {
+    b->dargs[q] = static_cast<GemmArgs*>(upload(args[q].data(), sizeof(GemmArgs) * cnt));
+    if (!b->dargs[q]) return set_error(SFISTA_ERR_NOMEM, "batch allocation failed");
+  }
+  b->depi[0] = upload(e0.data(), sizeof(e0[0]) * cnt);
+  b->depi[1] = upload(e1.data(), sizeof(e1[0]) * cnt);
+  b->depi[2] = upload(e2.data(), sizeof(e2[0]) * cnt);
+  if (b->kind == ST_F64) b->depi[3] = upload(u64.data(), sizeof(u64[0]) * cnt);
+  else if (b->kind == ST_PAIR) b->depi[3] = upload(upr.data(), sizeof(upr[0]) * cnt);
+  else b->depi[3] = upload(u32.data(), sizeof(u32[0]) * cnt);
+  if (!b->depi[0] || !b->depi[1] || !b->depi[2] || !b->depi[3]) return set_error(SFISTA_ERR_NOMEM, "batch allocation failed");
+  // work lists: problems with the longest K first, tiles of one problem together
+  for (int q = 0; q < 4; ++q) {
+    std::vector<int> order(cnt);
+    for (int i = 0; i < cnt; ++i) order[i] = i;
+    std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return args[q][x].K > args[q][y].K; });
+    for (int c = 0; c < 2; ++c) {
+      const int BM = c ? TileS::BM : TileL::BM, BN = c ? TileS::BN : TileL::BN;
+      std::vector<WorkItem> w;
+      for (int i : order) {
+        const int tm_n = (args[q][i].M + BM - 1) / BM, tn_n = (args[q][i].N + BN - 1) / BN;
+        for (int tm = 0; tm < tm_n; ++tm)
+          for (int tn = 0; tn < tn_n; ++tn) w.push_back(WorkItem{i, tm, tn, 0});
+      }
+      b->nwork[q][c] = (int)w.size();
+      b->dwork[q][c] = static_cast<WorkItem*>(upload(w.data(), sizeof(WorkItem) * w.size()));
+      if (!b->dwork[q][c]) return set_error(SFISTA_ERR_NOMEM, "batch allocation failed");
+    }
+  }
+  return SFISTA_OK;
+}
+
+// Times both tile shapes of every product on the batch itself and keeps the
+// faster; the state is reset afterwards.
+template <int MODE>
+hipError_t batch_autotune(sfista_batch* b) {
+  hipEvent_t e0, e1;
+  hipError_t e;
+  if ((e = hipEventCreate(&e0)) != hipSuccess) return e;
+  if ((e = hipEventCreate(&e1)) != hipSuccess) return e;
+  for (int q = 0; q < 4; ++q) {
+    float best = 1e30f;
+    int pick = 0;
+    for (int c = 0; c < 2; ++c) {
+      b->choice[q] = c;
+      for (int rep = 0; rep < 4; ++rep) {
+        if (rep == 1) (void)hipEventRecord(e0, b->s);
+        if (q == 0 || q == 2) e = launch_product<MODE, EpiStack<MODE>>(b, q);
+        else if (q == 1) e = launch_product<MODE, EpiResid<MODE>>(b, q);
+        else if (b->kind == ST_F64) e = launch_product<MODE, EpiUpdateSeq<MODE, ST_F64>>(b, q);
+        else if (b->kind == ST_PAIR) e = launch_product<MODE, EpiUpdateSeq<MODE, ST_PAIR>>(b, q);
+        else e = launch_product<MODE, EpiUpdateSeq<MODE, ST_F32>>(b, q);
+        if (e != hipSuccess) return e;
+      }
+      (void)hipEventRecord(e1, b->s);
+      if ((e = hipEventSynchronize(e1)) != hipSuccess) return e;
+      float ms = 0.f;
+      (void)hipEventElapsedTime(&ms, e0, e1);
+      if (ms < best) { best = ms; pick = c; }
+    }
+    b->choice[q] = pick;
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  for (sfista_plan* h : b->plans)
+    hipLaunchKernelGGL(init_state_kernel<MODE>, dim3(EW_BLOCKS), dim3(EW_THREADS), 0, b->s, nullptr, h->st[0],
+                       h->st[1], h->kind, h->Y[0], h->Y[1], h->ldY, h->m, h->n);
+  return hipGetLastError();
+}
+
+std::string batch_key(const sfista_batch* b) {
+  std::ostringstream k;
+  k << "m" << b->mode << "k" << b->kind;
+  for (const sfista_plan* h : b->plans) k << "_" << h->m << "x" << h->n << "r" << h->r;
+  std::hash<std::string> hs;
+  std::ostringstream o;
+  o << std::hex << hs(k.str());
+  return o.str();
+}
+
+bool tune_cache_lookup(const std::string& key, int* choice) {
+  const char* path = getenv("SFISTA_TUNE_CACHE");
+  if (!path || !*path) return false;
+  std::ifstream f(path);
+  std::string line;
+  while (std::getline(f, line)) {
+    std::istringstream ls(line);
+    std::string k;
+    int c[4];
+    if ((ls >> k >> c[0] >> c[1] >> c[2] >> c[3]) && k == key) {
+      for (int q = 0; q < 4; ++q) choice[q] = c[q] ? 1 : 0;
+      return true;
+    }
+  }
+  return false;
+}
+
+void tune_cache_store(const std::string& key, const int* choice) {
+  const char* path = getenv("SFISTA_TUNE_CACHE");
+  if (!path || !*path) return;
+  std::ofstream f(path, std::ios::app);
+  f << key << " " << choice[0] << " " << choice[1] << " " << choice[2] << " " << choice[3] << "\n";
+}
+
+template <int MODE>
+int batch_setup_mode(sfista_batch* b) {
+  int rc = batch_build<MODE>(b);
+  if (rc != SFISTA_OK) return rc;
+  // default shape: the 128 x 128 tile unless it leaves most CUs idle
+  int cus = 256, dev = 0;
+  hipDeviceProp_t prop;
+  if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess) cus = prop.multiProcessorCount;
+  for (int q = 0; q < 4; ++q) b->choice[q] = b->nwork[q][0] >= 2 * cus ? 0 : 1;
+  if (b->flags & SFISTA_BATCH_AUTOTUNE) {
+    const std::string key = batch_key(b);
+    if (!tune_cache_lookup(key, b->choice)) {
+      hipError_t e = batch_autotune<MODE>(b);
+      if (e != hipSuccess) return hip_fail(e, "batch autotune");
+      tune_cache_store(key, b->choice);
+    }
+  }
+  hipError_t e = hipStreamSynchronize(b->s);
+  if (e != hipSuccess) return hip_fail(e, "batch setup");
+  return SFISTA_OK;
+}
+
+template <int MODE>
+hipError_t batch_run(sfista_batch* b, int iters) {
+  hipError_t e = hipSuccess;
+  int left = iters;
+  if ((b->flags & SFISTA_BATCH_GRAPH) && left >= GRAPH_ITERS) {
+    if (!b->gexec) {
+      if ((e = hipStreamBeginCapture(b->s, hipStreamCaptureModeRelaxed)) != hipSuccess) return e;
+      for (int i = 0; i < GRAPH_ITERS && e == hipSuccess; ++i) e = batch_iteration<MODE>(b);
+      hipGraph_t g = nullptr;
+      const hipError_t ec = hipStreamEndCapture(b->s, &g);
+      if (e != hipSuccess) return e;
+      if (ec != hipSuccess) return ec;
+      b->graph = g;
+      if ((e = hipGraphInstantiate(&b->gexec, b->graph, nullptr, nullptr, 0)) != hipSuccess) return e;
+    }
+    while (left >= GRAPH_ITERS) {
+      if ((e = hipGraphLaunch(b->gexec, b->s)) != hipSuccess) return e;
+      left -= GRAPH_ITERS;
+    }
+  }
+  for (int i = 0; i < left && e == hipSuccess; ++i) e = batch_iteration<MODE>(b);
+  return e;
+}
+
+}  // namespace
+
+extern "C" {
+
+int sfista_batch_setup(const sfista_batch_item* items, int count, const sfista_params* common, int max_iters,
+                       int flags, hipStream_t stream, sfista_batch_handle* out) {
+  clear_error();
+  if (!out) return set_error(SFISTA_ERR_ARG, "out handle pointer is NULL");
+  *out = nullptr;
+  if (!items || !common || count < 1) return set_error(SFISTA_ERR_ARG, "items, common and count >= 1 required");
+  if (max_iters < 1 || max_iters > (1 << 24)) return set_error(SFISTA_ERR_ARG, "max_iters must lie in [1, 2^24]");
+  if (common->precision < SFISTA_FP64 || common->precision > SFISTA_BF16X3)
+    return set_error(SFISTA_ERR_UNSUPPORTED, "unknown precision %d", common->precision);
+  if (common->x0 || common->v0) return set_error(SFISTA_ERR_UNSUPPORTED, "batch problems start from X_0 = 0 and an internal power start");
+  for (int i = 0; i < count; ++i) {
+    sfista_params p = *common;
+    p.lambda = items[i].lambda;
+    p.L = items[i].L;
+    const int rc = validate_problem(items[i].Bobs, items[i].m, items[i].n, items[i].A, items[i].B, items[i].r, &p);
+    if (rc != SFISTA_OK) {
+      std::string msg = last_error_slot();
+      return set_error(rc, "batch problem %d: %s", i, msg.c_str());
+    }
+  }
+  sfista_batch* b = new (std::nothrow) sfista_batch();
+  if (!b) return set_error(SFISTA_ERR_NOMEM, "host allocation failed");
+  b->count = count; b->mode = common->precision; b->kind = state_kind(b->mode, common->pair_state);
+  b->max_iters = max_iters; b->flags = flags;
+  hipError_t e;
+  if ((e = hipStreamSynchronize(stream)) != hipSuccess || (e = hipStreamCreateWithFlags(&b->s, hipStreamNonBlocking)) != hipSuccess) {
+    delete b;
+    return hip_fail(e, "batch stream");
+  }
+  for (int i = 0; i < count; ++i) {
+    sfista_params p = *common;
+    p.lambda = items[i].lambda;
+    p.L = items[i].L;
+    sfista_handle h = nullptr;
+    const int rc = sfista_setup(items[i].Bobs, items[i].m, items[i].n, items[i].A, items[i].B, items[i].r, &p, b->s, &h);
+    if (rc != SFISTA_OK) {
+      std::string msg = last_error_slot();
+      delete b;
+      return set_error(rc, "batch problem %d: %s", i, msg.c_str());
+    }
+    b->plans.push_back(h);
+  }
+  // momentum table and iteration counter
+  std::vector<double> beta(max_iters + 2, 0.0);
+  double t = 1.0;
+  for (int k = 1; k <= max_iters + 1; ++k) {
+    const double tn = (1.0 + sqrt(1.0 + 4.0 * t * t)) / 2.0;
+    beta[k] = (t - 1.0) / tn;
+    t = tn;
+  }
+  b->beta = static_cast<double*>(b->arena.alloc_zero(beta.size() * sizeof(double), b->s));
+  b->counter = static_cast<int*>(b->arena.alloc_zero(256, b->s));
+  if (!b->beta || !b->counter) {
+    delete b;
+    return set_error(SFISTA_ERR_NOMEM, "batch allocation failed");
+  }
+  if ((e = hipMemcpyAsync(b->beta, beta.data(), beta.size() * sizeof(double), hipMemcpyHostToDevice, b->s)) != hipSuccess) {
+    delete b;
+    return hip_fail(e, "batch upload");
+  }
+  int rc = SFISTA_OK;
+  SF_DISPATCH(b->mode, rc = batch_setup_mode<MD>(b));
+  if (rc != SFISTA_OK) {
+    delete b;
+    return rc;
+  }
+  *out = b;
+  return SFISTA_OK;
+}
+
+int sfista_batch_solve(sfista_batch_handle b, int iters, double* const* X_out, sfista_report* reps) {
+  clear_error();
+  if (!b) return set_error(SFISTA_ERR_ARG, "NULL handle");
+  if (iters < 0 || b->iter + iters > b->max_iters)
+    return set_error(SFISTA_ERR_ARG, "iterations beyond the batch's max_iters (%d)", b->max_iters);
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  hipError_t e;
+  if ((e = hipEventCreate(&e0)) != hipSuccess || (e = hipEventCreate(&e1)) != hipSuccess) return hip_fail(e, "event");
+  (void)hipEventRecord(e0, b->s);
+  SF_DISPATCH(b->mode, e = batch_run<MD>(b, iters));
+  (void)hipEventRecord(e1, b->s);
+  if (e == hipSuccess) e = hipEventSynchronize(e1);
+  float ms = 0.f;
+  if (e == hipSuccess) (void)hipEventElapsedTime(&ms, e0, e1);
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (e != hipSuccess) return hip_fail(e, "sfista_batch_solve iterations");
+  b->iter += iters;
+  int status = SFISTA_OK;
+  for (int i = 0; i < b->count; ++i) {
+    sfista_plan* h = b->plans[i];
+    h->iter = b->iter;
+    double rr = 0.0, xx = 0.0;
+    SF_DISPATCH(h->mode, e = report_mode<MD>(h, &rr, &xx));
+    if (e != hipSuccess) return hip_fail(e, "sfista_batch_solve report");
+    const long mn = (long)h->m * h->n;
+    if (X_out && X_out[i]) {
+      hipLaunchKernelGGL(state_to_double_kernel, dim3(EW_BLOCKS), dim3(EW_THREADS), 0, h->s, h->st[h->iter & 1],
+                         h->kind, X_out[i], mn);
+      if ((e = hipStreamSynchronize(h->s)) != hipSuccess) return hip_fail(e, "copy X");
+    }
+    const double phi = 0.5 * rr + 0.5 * h->lam * h->lam * xx;
+    int st = SFISTA_OK;
+    if (!isfinite(phi)) st = status = set_error(SFISTA_ERR_NONFINITE, "problem %d: objective is not finite", i);
+    if (reps) {
+      reps[i].iters = (int)b->iter;
+      reps[i].seconds = ms * 1e-3;
+      reps[i].L = h->L;
+      reps[i].phi_s = phi;
+      reps[i].resid_norm = sqrt(rr);
+      reps[i].bobs_norm = h->bobs_norm;
+      reps[i].x_norm = sqrt(xx);
+      reps[i].resid_rel = h->bobs_norm > 0 ? sqrt(rr) / h->bobs_norm : 0.0;
+      reps[i].status = st;
+    }
+  }
+  return status;
+}
+
+int sfista_batch_tiles(sfista_batch_handle b, int* choice) {
+  clear_error();
+  if (!b || !choice) return set_error(SFISTA_ERR_ARG, "NULL argument");
+  for (int q = 0; q < 4; ++q) choice[q] = b->choice[q];
+  return SFISTA_OK;
+}
+
+void sfista_batch_destroy(sfista_batch_handle b) { delete b; }
 
 }  // extern "C"

@@ -32,7 +32,11 @@ PRECISIONS = {"fp64": 0, "fp32": 1, "bf16": 2, "fp16": 3, "bf16x3": 4}
 
 EXPORTS = ("kron_approx", "sfista_setup", "sfista_step", "sfista_solve", "sfista_apply",
            "sfista_set_timing", "sfista_kernel_times", "sfista_get_L", "sfista_destroy",
-           "sfista_last_error")
+           "sfista_last_error", "sfista_batch_setup", "sfista_batch_solve", "sfista_batch_tiles",
+           "sfista_batch_destroy")
+
+BATCH_AUTOTUNE = 1
+BATCH_GRAPH = 2
 
 
 class SfistaError(RuntimeError):
@@ -45,6 +49,11 @@ class Params(ctypes.Structure):
     _fields_ = [("lambda_", ctypes.c_double), ("L", ctypes.c_double), ("precision", ctypes.c_int),
                 ("nonneg", ctypes.c_int), ("power_iters", ctypes.c_int), ("pair_state", ctypes.c_int),
                 ("x0", ctypes.c_void_p), ("v0", ctypes.c_void_p)]
+
+
+class BatchItem(ctypes.Structure):
+    _fields_ = [("Bobs", ctypes.c_void_p), ("m", ctypes.c_int), ("n", ctypes.c_int), ("A", ctypes.c_void_p),
+                ("B", ctypes.c_void_p), ("r", ctypes.c_int), ("lambda_", ctypes.c_double), ("L", ctypes.c_double)]
 
 
 class Report(ctypes.Structure):
@@ -79,10 +88,17 @@ def lib() -> ctypes.CDLL:
     L.sfista_kernel_times.argtypes = [vp, ctypes.POINTER(d), ctypes.POINTER(ctypes.c_long)]
     L.sfista_destroy.argtypes = [vp]
     L.sfista_destroy.restype = None
+    L.sfista_batch_setup.argtypes = [ctypes.POINTER(BatchItem), i, ctypes.POINTER(Params), i, i, vp,
+                                     ctypes.POINTER(vp)]
+    L.sfista_batch_solve.argtypes = [vp, i, ctypes.POINTER(vp), ctypes.POINTER(Report)]
+    L.sfista_batch_tiles.argtypes = [vp, ctypes.POINTER(i)]
+    L.sfista_batch_destroy.argtypes = [vp]
+    L.sfista_batch_destroy.restype = None
     L.sfista_last_error.argtypes = []
     L.sfista_last_error.restype = ctypes.c_char_p
     for name in ("kron_approx", "sfista_setup", "sfista_step", "sfista_solve", "sfista_apply", "sfista_get_L",
-                 "sfista_set_timing", "sfista_kernel_times"):
+                 "sfista_set_timing", "sfista_kernel_times", "sfista_batch_setup", "sfista_batch_solve",
+                 "sfista_batch_tiles"):
         getattr(L, name).restype = ctypes.c_int
     _lib = L
     return L
@@ -186,6 +202,66 @@ class Solver:
     def close(self):
         if self._h is not None:
             lib().sfista_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Batch:
+    """Many independent sFISTA problems advanced together (Algorithm 2 on
+    each): every GEMM phase of one iteration is a single grouped launch over
+    all problems.  ``problems`` is a sequence of ``(Bobs, A, B, lam, L)`` with
+    device float64 tensors; ``L = None`` estimates it by ``power_iters`` power
+    steps.  ``autotune`` times both tile shapes per phase on the batch itself;
+    ``graph`` replays the iterations from a captured HIP graph."""
+
+    def __init__(self, problems, precision: str = "bf16x3", max_iters: int = 1000, nonneg: bool = False,
+                 power_iters: int = 0, pair_state: bool = True, autotune: bool = False, graph: bool = False,
+                 stream=None):
+        items = (BatchItem * max(len(problems), 1))()
+        self.shapes = []
+        self.device = None
+        for k, (Bobs, A, B, lam, L) in enumerate(problems):
+            m, n = Bobs.shape
+            r = A.shape[0]
+            if A.shape != (r, n, n) or B.shape != (r, m, m):
+                raise ValueError(f"problem {k}: A must be (r, n, n) and B (r, m, m) for Bobs of shape (m, n)")
+            items[k] = BatchItem(_dev_f64(Bobs, "Bobs"), m, n, _dev_f64(A, "A"), _dev_f64(B, "B"), r,
+                                 float(lam), float(L) if L is not None else 0.0)
+            self.shapes.append((m, n))
+            self.device = Bobs.device
+        common = Params(0.0, 0.0, PRECISIONS[precision], int(bool(nonneg)), int(power_iters),
+                        int(bool(pair_state)), None, None)
+        flags = (BATCH_AUTOTUNE if autotune else 0) | (BATCH_GRAPH if graph else 0)
+        h = ctypes.c_void_p()
+        self._h = None
+        _check(lib().sfista_batch_setup(items, len(problems), ctypes.byref(common), int(max_iters), flags,
+                                        _stream(stream), ctypes.byref(h)))
+        self._h = h
+
+    def solve(self, iters: int, want_x: bool = True):
+        """Run ``iters`` more iterations; returns (list of X or None, list of report dicts)."""
+        import torch
+        cnt = len(self.shapes)
+        xs = [torch.empty(s, dtype=torch.float64, device=self.device) for s in self.shapes] if want_x else None
+        ptrs = (ctypes.c_void_p * cnt)(*[x.data_ptr() for x in xs]) if want_x else None
+        reps = (Report * cnt)()
+        _check(lib().sfista_batch_solve(self._h, int(iters), ptrs, reps))
+        return xs, [r.as_dict() for r in reps]
+
+    def tiles(self):
+        """Tile shape chosen per phase (F1, F2, G1, G2): 0 = 128 x 128, 1 = 64 x 64."""
+        c = (ctypes.c_int * 4)()
+        _check(lib().sfista_batch_tiles(self._h, c))
+        return list(c)
+
+    def close(self):
+        if self._h is not None:
+            lib().sfista_batch_destroy(self._h)
             self._h = None
 
     def __del__(self):

@@ -89,3 +89,45 @@ def test_handle_calls_reject_null(L):
     assert L.sfista_solve(None, 1, 0.0, None, None) == -1
     assert L.sfista_apply(None, FAKE, None, None) == -1
     L.sfista_destroy(None)
+
+
+def _items(count=2, **kw):
+    from paper_1901_00913_amd.sfista import BatchItem
+    arr = (BatchItem * count)()
+    for i in range(count):
+        arr[i] = BatchItem(FAKE, 8, 8, FAKE, FAKE, 2, 0.01, 1.0)
+    for k, v in kw.items():
+        setattr(arr[count - 1], k, v)
+    return arr
+
+
+@pytest.mark.parametrize("count,max_iters,item,common,expect", [
+    (0, 10, {}, {}, -1),                          # empty batch
+    (2, 0, {}, {}, -1),                           # no iterations allowed
+    (2, 10, dict(m=0), {}, -1),                   # bad size in the last problem
+    (2, 10, dict(r=9), {}, -1),                   # r > min(m, n)
+    (2, 10, dict(lambda_=-0.5), {}, -1),
+    (2, 10, dict(L=float("nan")), {}, -1),
+    (2, 10, dict(Bobs=None), {}, -1),
+    (2, 10, {}, dict(precision=9), -2),
+    (2, 10, {}, dict(x0=0x2000), -2),             # batch problems start from zero
+    (2, 10, {}, dict(power_iters=-2), -1),
+])
+def test_batch_setup_rejects_invalid_arguments(L, count, max_iters, item, common, expect):
+    items = _items(max(count, 1), **item)
+    p = _params(**common)
+    h = ctypes.c_void_p()
+    rc = L.sfista_batch_setup(items, count, ctypes.byref(p), max_iters, 0, None, ctypes.byref(h))
+    assert rc == expect
+    assert h.value is None
+    assert L.sfista_last_error()
+
+
+def test_batch_calls_reject_null(L):
+    p = _params()
+    assert L.sfista_batch_setup(None, 2, ctypes.byref(p), 10, 0, None, ctypes.byref(ctypes.c_void_p())) == -1
+    assert L.sfista_batch_setup(_items(), 2, None, 10, 0, None, ctypes.byref(ctypes.c_void_p())) == -1
+    assert L.sfista_batch_setup(_items(), 2, ctypes.byref(p), 10, 0, None, None) == -1
+    assert L.sfista_batch_solve(None, 1, None, None) == -1
+    assert L.sfista_batch_tiles(None, (ctypes.c_int * 4)()) == -1
+    L.sfista_batch_destroy(None)
