@@ -57,6 +57,77 @@ def measured_traffic(gemm_index, precision, m, n, r):
     return float(vals["traffic_bytes"])
 
 
+BATCH_COUNT = 64
+BATCH_ITERS = 100
+
+
+def run_batch(args, dev, steps, warmup):
+    """64 uneven problems (square n in 128..1024, own PSF, rank 1..8, own
+    lambda) in plain FP32: per step, the Kronecker approximation of every
+    PSF, the batch setup (power iteration for every L, tile autotuning with
+    a cache file) and 100 iterations replayed from a HIP graph."""
+    import tempfile
+
+    import numpy as np
+    import torch
+
+    import synth as S
+    from paper_1901_00913_amd import sfista
+
+    if not os.environ.get("SFISTA_TUNE_CACHE"):
+        os.environ["SFISTA_TUNE_CACHE"] = os.path.join(tempfile.gettempdir(), f"sfista_tune_{os.getpid()}.txt")
+    log(f"[batch] generating {BATCH_COUNT} problems")
+    probs = S.batch_problems(count=BATCH_COUNT, iters=BATCH_ITERS)
+    psf = [torch.as_tensor(p.psf).to(dev) for p in probs]
+    bobs = [torch.as_tensor(p.bobs).to(dev) for p in probs]
+    flops_iter = sum(4.0 * p.r * p.shape[0] * p.shape[1] * (p.shape[0] + p.shape[1]) for p in probs)
+    torch.cuda.synchronize()
+
+    def step():
+        items = []
+        for p, P, Bo in zip(probs, psf, bobs):
+            l, q = p.center
+            A, B, _, _ = sfista.kron_approx(P, l, q, p.bc, p.r)
+            items.append((Bo, A, B, p.lam, None))
+        b = sfista.Batch(items, precision="fp32", pair_state=False, max_iters=BATCH_ITERS, power_iters=30,
+                         autotune=True, graph=True)
+        _, reps = b.solve(BATCH_ITERS, want_x=False)
+        tiles = b.tiles()
+        b.close()
+        return reps, tiles
+
+    for w in range(warmup):
+        log(f"[batch] warmup step {w + 1}/{warmup}")
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    out = [step() for _ in range(steps)]
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    iter_s = float(np.mean([o[0][0]["seconds"] for o in out]))
+    value = BATCH_COUNT * BATCH_ITERS * steps / elapsed
+    achieved = flops_iter * BATCH_ITERS / iter_s / 1e12
+    peak = PEAK_TFLOPS["fp32"]
+    log(f"[batch] {steps} steps in {elapsed:.3f} s -> {value:.0f} image-iters/s; iterations {achieved:.1f} TFLOP/s")
+    summary = {"image_iters_per_s": value, "iteration_only_image_iters_per_s": BATCH_COUNT * BATCH_ITERS / iter_s,
+               "iteration_alg_tflops": achieved, "fp32_mfma_frac": achieved / peak, "tiles": out[-1][1],
+               "ms_per_step": elapsed / steps * 1e3, "max_resid_rel": max(r["resid_rel"] for r in out[-1][0])}
+    line = {
+        "metric": "sFISTA image-iterations/s, 64 uneven images in one batch", "value": value,
+        "unit": "image-iters/s", "n_gpus": 1, "steps": steps, "warmup": warmup,
+        "ms_per_step": elapsed / steps * 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "fp32", "data": "synthetic",
+        "config": {"workload": f"sfista-batch{BATCH_COUNT}-n128..1024-r1..8-{BATCH_ITERS}it",
+                   "images": BATCH_COUNT, "iters": BATCH_ITERS, "precision": "fp32", "parallelism": "single-gpu"},
+        "roofline": {"bound": "mfma", "kernel": "gemm_grouped (all four phases, whole iterations)",
+                     "achieved": achieved, "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak,
+                     "traffic": None},
+        "cpu_baseline": None,
+        "extra": summary,
+    }
+    return {"line": line, "summary": summary}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -69,6 +140,10 @@ def main():
     ap.add_argument("--cpu-iters", type=int, default=3, help="oracle iterations timed for cpu_baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp32-compare", action="store_true")
+    ap.add_argument("--workload", default="precision-2048", choices=("precision-2048", "batch64"),
+                    help="precision-2048: one 2048^2 image, r = 5 (default); batch64: 64 uneven images "
+                         "in grouped launches replayed from a HIP graph")
+    ap.add_argument("--no-batch", action="store_true", help="skip the batch64 summary in the default line")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="after the timed steps, copy a BYTES-long device buffer once (a plain copy kernel "
                          "of known traffic, for scaling hardware byte counters)")
@@ -90,6 +165,11 @@ def main():
         sys.exit(2)
     sfista.lib()
     dev = torch.device("cuda:0")
+
+    if args.workload == "batch64":
+        res = run_batch(args, dev, args.steps, args.warmup)
+        print(json.dumps(res["line"]), flush=True)
+        return
 
     log(f"[bench] generating the {args.n}x{args.n} workload")
     p = S.config(3, n=args.n, iters=args.iters)
@@ -195,6 +275,9 @@ def main():
                          f"(Kronecker setup excluded)",
                "rel_err_gpu_vs_oracle": rel_err, "rel_err_iters": args.cpu_iters}
         log(f"[bench] cpu_baseline {cpu['value']:.3f} it/s on {threads} threads; rel err {rel_err:.3e}")
+
+    if not args.no_batch:
+        extra["batch64"] = run_batch(args, dev, 1, 1)["summary"]
 
     out = {
         "metric": METRIC, "value": value, "unit": "iters/s", "n_gpus": 1, "steps": args.steps,

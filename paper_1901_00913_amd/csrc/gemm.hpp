@@ -11,8 +11,8 @@
 //
 // One workgroup computes a BM x BN tile with (BM/WM) x (BN/WN) wavefronts of
 // 64 lanes; each wave owns a WM x WN sub-tile made of 16x16 MFMA blocks.  K is
-// walked in stages of 64 bytes per row through an NS-deep ring of LDS
-// buffers filled by direct global-to-LDS loads (see gemm_nt_kernel).
+// walked in stages of 64 bytes per row through two LDS buffers filled by
+// direct global-to-LDS loads (see gemm_tile).
 //
 // Every mode consumes a 16-byte chunk per lane per 64-byte K segment:
 //   BF16/FP16 : 8 values  -> one v_mfma_f32_16x16x32_{bf16,f16}
@@ -27,6 +27,9 @@
 // the f32-accumulating instructions, (l/16) + 4*t for the f64 one
 // (t = 0..3, the accumulator register).
 #pragma once
+
+#include <algorithm>
+#include <vector>
 
 #include "common.hpp"
 
@@ -80,138 +83,6 @@ __device__ __forceinline__ void mma_chunk(typename AccVec<MODE>::T& acc, const u
   }
 }
 
-// Workgroup -> tile.  Workgroups are dispatched round-robin over the 8 XCDs
-// (id % 8); the first remap gives every XCD a contiguous range of tile ids so
-// that tiles sharing A or B panels share that XCD's L2.  Within the range,
-// tiles are walked in column groups of GROUP_M tile-rows.
-__device__ __forceinline__ void map_tile(int bid, int nblk, int tiles_m, int tiles_n, int& tm, int& tn) {
-  int t = bid;
-  if ((nblk & 7) == 0) {
-    const int per = nblk >> 3;
-    t = (bid & 7) * per + (bid >> 3);
-  }
-  constexpr int GROUP_M = 8;
-  const int width = GROUP_M * tiles_n;
-  const int group = t / width;
-  const int first_m = group * GROUP_M;
-  const int gm = min(tiles_m - first_m, GROUP_M);
-  const int inner = t - group * width;
-  tm = first_m + inner % gm;
-  tn = inner / gm;
-}
-
-
-// Fragment loads of one stage: P planes x (FM A + FN B) 16-byte LDS reads,
-// issued back to back in one asm block that ends with its own lgkmcnt wait,
-// so every read has retired when the block ends.  Keeping these reads out of
-// the compiler's sight stops its conservative wait on the in-flight
-// global-to-LDS loads of later stages (their ordering is enforced by the
-// explicit vmcnt wait and barrier at the top of each stage).
-template <int P, int FM, int FN> struct FragLoad;
-
-#define SF_R(o, a, off) "ds_read_b128 %" #o ", %" #a " offset:" #off "\n\t"
-template <> struct FragLoad<1, 4, 2> {
-  static __device__ __forceinline__ void run(uint4 (&fa)[4][1], uint4 (&fb)[2][1], const unsigned (&ra)[1],
-                                             const unsigned (&rb)[1]) {
-    asm volatile(SF_R(0, 6, 0) SF_R(1, 6, 1024) SF_R(2, 6, 2048) SF_R(3, 6, 3072) SF_R(4, 7, 0) SF_R(5, 7, 1024)
-                 "s_waitcnt lgkmcnt(0)"
-                 : "=&v"(fa[0][0]), "=&v"(fa[1][0]), "=&v"(fa[2][0]), "=&v"(fa[3][0]), "=&v"(fb[0][0]), "=&v"(fb[1][0])
-                 : "v"(ra[0]), "v"(rb[0])
-                 : "memory");
-  }
-};
-template <> struct FragLoad<2, 4, 2> {
-  static __device__ __forceinline__ void run(uint4 (&fa)[4][2], uint4 (&fb)[2][2], const unsigned (&ra)[2],
-                                             const unsigned (&rb)[2]) {
-    asm volatile(SF_R(0, 12, 0) SF_R(1, 12, 1024) SF_R(2, 12, 2048) SF_R(3, 12, 3072) SF_R(4, 13, 0)
-                 SF_R(5, 13, 1024) SF_R(6, 14, 0) SF_R(7, 14, 1024) SF_R(8, 14, 2048) SF_R(9, 14, 3072)
-                 SF_R(10, 15, 0) SF_R(11, 15, 1024)
-                 "s_waitcnt lgkmcnt(0)"
-                 : "=&v"(fa[0][0]), "=&v"(fa[1][0]), "=&v"(fa[2][0]), "=&v"(fa[3][0]), "=&v"(fb[0][0]), "=&v"(fb[1][0]),
-                   "=&v"(fa[0][1]), "=&v"(fa[1][1]), "=&v"(fa[2][1]), "=&v"(fa[3][1]), "=&v"(fb[0][1]), "=&v"(fb[1][1])
-                 : "v"(ra[0]), "v"(rb[0]), "v"(ra[1]), "v"(rb[1])
-                 : "memory");
-  }
-};
-template <> struct FragLoad<1, 4, 4> {
-  static __device__ __forceinline__ void run(uint4 (&fa)[4][1], uint4 (&fb)[4][1], const unsigned (&ra)[1],
-                                             const unsigned (&rb)[1]) {
-    asm volatile(SF_R(0, 8, 0) SF_R(1, 8, 1024) SF_R(2, 8, 2048) SF_R(3, 8, 3072) SF_R(4, 9, 0) SF_R(5, 9, 1024)
-                 SF_R(6, 9, 2048) SF_R(7, 9, 3072)
-                 "s_waitcnt lgkmcnt(0)"
-                 : "=&v"(fa[0][0]), "=&v"(fa[1][0]), "=&v"(fa[2][0]), "=&v"(fa[3][0]), "=&v"(fb[0][0]), "=&v"(fb[1][0]),
-                   "=&v"(fb[2][0]), "=&v"(fb[3][0])
-                 : "v"(ra[0]), "v"(rb[0])
-                 : "memory");
-  }
-};
-template <> struct FragLoad<2, 4, 4> {
-  static __device__ __forceinline__ void run(uint4 (&fa)[4][2], uint4 (&fb)[4][2], const unsigned (&ra)[2],
-                                             const unsigned (&rb)[2]) {
-    asm volatile(SF_R(0, 16, 0) SF_R(1, 16, 1024) SF_R(2, 16, 2048) SF_R(3, 16, 3072) SF_R(4, 17, 0)
-                 SF_R(5, 17, 1024) SF_R(6, 17, 2048) SF_R(7, 17, 3072) SF_R(8, 18, 0) SF_R(9, 18, 1024)
-                 SF_R(10, 18, 2048) SF_R(11, 18, 3072) SF_R(12, 19, 0) SF_R(13, 19, 1024) SF_R(14, 19, 2048)
-                 SF_R(15, 19, 3072)
-                 "s_waitcnt lgkmcnt(0)"
-                 : "=&v"(fa[0][0]), "=&v"(fa[1][0]), "=&v"(fa[2][0]), "=&v"(fa[3][0]), "=&v"(fb[0][0]), "=&v"(fb[1][0]),
-                   "=&v"(fb[2][0]), "=&v"(fb[3][0]), "=&v"(fa[0][1]), "=&v"(fa[1][1]), "=&v"(fa[2][1]), "=&v"(fa[3][1]),
-                   "=&v"(fb[0][1]), "=&v"(fb[1][1]), "=&v"(fb[2][1]), "=&v"(fb[3][1])
-                 : "v"(ra[0]), "v"(rb[0]), "v"(ra[1]), "v"(rb[1])
-                 : "memory");
-  }
-};
-template <> struct FragLoad<1, 2, 4> {
-  static __device__ __forceinline__ void run(uint4 (&fa)[2][1], uint4 (&fb)[4][1], const unsigned (&ra)[1],
-                                             const unsigned (&rb)[1]) {
-    asm volatile(SF_R(0, 6, 0) SF_R(1, 6, 1024) SF_R(2, 7, 0) SF_R(3, 7, 1024) SF_R(4, 7, 2048) SF_R(5, 7, 3072)
-                 "s_waitcnt lgkmcnt(0)"
-                 : "=&v"(fa[0][0]), "=&v"(fa[1][0]), "=&v"(fb[0][0]), "=&v"(fb[1][0]), "=&v"(fb[2][0]), "=&v"(fb[3][0])
-                 : "v"(ra[0]), "v"(rb[0])
-                 : "memory");
-  }
-};
-template <> struct FragLoad<2, 2, 4> {
-  static __device__ __forceinline__ void run(uint4 (&fa)[2][2], uint4 (&fb)[4][2], const unsigned (&ra)[2],
-                                             const unsigned (&rb)[2]) {
-    asm volatile(SF_R(0, 12, 0) SF_R(1, 12, 1024) SF_R(2, 13, 0) SF_R(3, 13, 1024) SF_R(4, 13, 2048)
-                 SF_R(5, 13, 3072) SF_R(6, 14, 0) SF_R(7, 14, 1024) SF_R(8, 15, 0) SF_R(9, 15, 1024)
-                 SF_R(10, 15, 2048) SF_R(11, 15, 3072)
-                 "s_waitcnt lgkmcnt(0)"
-                 : "=&v"(fa[0][0]), "=&v"(fa[1][0]), "=&v"(fb[0][0]), "=&v"(fb[1][0]), "=&v"(fb[2][0]), "=&v"(fb[3][0]),
-                   "=&v"(fa[0][1]), "=&v"(fa[1][1]), "=&v"(fb[0][1]), "=&v"(fb[1][1]), "=&v"(fb[2][1]), "=&v"(fb[3][1])
-                 : "v"(ra[0]), "v"(rb[0]), "v"(ra[1]), "v"(rb[1])
-                 : "memory");
-  }
-};
-template <> struct FragLoad<1, 2, 2> {
-  static __device__ __forceinline__ void run(uint4 (&fa)[2][1], uint4 (&fb)[2][1], const unsigned (&ra)[1],
-                                             const unsigned (&rb)[1]) {
-    asm volatile(SF_R(0, 4, 0) SF_R(1, 4, 1024) SF_R(2, 5, 0) SF_R(3, 5, 1024)
-                 "s_waitcnt lgkmcnt(0)"
-                 : "=&v"(fa[0][0]), "=&v"(fa[1][0]), "=&v"(fb[0][0]), "=&v"(fb[1][0])
-                 : "v"(ra[0]), "v"(rb[0])
-                 : "memory");
-  }
-};
-template <> struct FragLoad<2, 2, 2> {
-  static __device__ __forceinline__ void run(uint4 (&fa)[2][2], uint4 (&fb)[2][2], const unsigned (&ra)[2],
-                                             const unsigned (&rb)[2]) {
-    asm volatile(SF_R(0, 8, 0) SF_R(1, 8, 1024) SF_R(2, 9, 0) SF_R(3, 9, 1024) SF_R(4, 10, 0) SF_R(5, 10, 1024)
-                 SF_R(6, 11, 0) SF_R(7, 11, 1024)
-                 "s_waitcnt lgkmcnt(0)"
-                 : "=&v"(fa[0][0]), "=&v"(fa[1][0]), "=&v"(fb[0][0]), "=&v"(fb[1][0]), "=&v"(fa[0][1]), "=&v"(fa[1][1]),
-                   "=&v"(fb[0][1]), "=&v"(fb[1][1])
-                 : "v"(ra[0]), "v"(rb[0]), "v"(ra[1]), "v"(rb[1])
-                 : "memory");
-  }
-};
-#undef SF_R
-
-// 32-bit LDS address of a pointer into __shared__ memory.
-__device__ __forceinline__ unsigned lds_addr(const void* p) {
-  return static_cast<unsigned>(reinterpret_cast<uintptr_t>((const __attribute__((address_space(3))) void*)p));
-}
-
 // s_waitcnt immediate that waits until at most N vector-memory operations
 // are outstanding (expcnt and lgkmcnt left at their no-wait maxima).
 template <int N>
@@ -220,95 +91,108 @@ constexpr int vmcnt_imm() {
   return (N & 0xF) | (0x7 << 4) | (0xF << 8) | ((N >> 4) << 14);
 }
 
-// LDS staging: NS stages, each holding 64 bytes of K for the BM + BN rows of
-// every plane, as the 1 KB blocks of the operand layout (op_index: 16 rows x
-// 64 K-bytes, chunk-major inside).  An MFMA fragment wants lane l to hold row
+// LDS staging: two buffers (two distinct __shared__ arrays, so the compiler
+// can tell the global-to-LDS copy into one from the fragment reads of the
+// other), each holding one stage of 64 K-bytes for the BM + BN rows of every
+// plane, as the 1 KB blocks of the operand layout (op_index: 16 rows x 64
+// K-bytes, chunk-major inside).  An MFMA fragment wants lane l to hold row
 // l % 16, chunk l / 16, i.e. byte 16 l of a block, so every fragment read is
 // one contiguous 1 KB wave access, the pattern the LDS serves at full rate
 // (16-row gathers from a row-major tile run at half rate on gfx950, with or
 // without padding or XOR swizzles).
 //
 // Global -> LDS uses gfx950's global_load_lds_dwordx4: one instruction copies
-// one contiguous 1 KB block (lane L moves bytes [16 L, 16 L + 16)).  Loads run
-// NS - 1 stages ahead; each stage starts with a wait until the wave's loads of
-// that stage have landed and a workgroup barrier that publishes all waves'
-// loads (and retires every wave's reads of the stage about to be refilled).
-// Workgroup layout: KG groups of (BM/WM) x (BN/WN) waves.  Every group
-// covers the whole BM x BN tile; per barrier the workgroup consumes G
-// stages and group q computes the stages gg = q (mod KG) of them, so the K
-// range is split inside the workgroup.  After the loop the groups add their
-// accumulators through LDS and group 0 runs the epilogue.  KG = 2 lets eight
-// waves share a 128 x 128 tile with 64 x 64 sub-tiles, which halves the LDS
-// fragment traffic per MFMA compared with 64 x 32 sub-tiles.
+// one contiguous 1 KB block (lane L moves bytes [16 L, 16 L + 16)).  Stage kt
+// lives in buffer kt % 2.  At the top of a stage each wave waits for its own
+// copies of that stage, a workgroup barrier publishes every wave's copies
+// (and retires all reads of the other buffer), and the copies of the next
+// stage into the other buffer are issued before this stage's MFMAs.  The
+// fragment reads are ordinary LDS loads, so the compiler interleaves them
+// with the MFMAs and waits for each fragment only where it is first used.
 template <int MODE, class T, class Epi>
-__device__ __forceinline__ void gemm_tile(unsigned char* lds, const GemmArgs& g, int tm, int tn, int kz,
-                                          const Epi& epi) {
+__device__ __forceinline__ void gemm_tile(unsigned char* lds0, unsigned char* lds1, const GemmArgs& g, int tm,
+                                          int tn, int kt0, int ktiles, const Epi& epi) {
   using Tr = ModeTraits<MODE>;
   using AccT = typename AccVec<MODE>::T;
-  using Acc = typename Tr::Acc;
-  constexpr int BM = T::BM, BN = T::BN, WM = T::WM, WN = T::WN, NS = T::NS, G = T::G, KG = T::KG;
+  constexpr int BM = T::BM, BN = T::BN, WM = T::WM, WN = T::WN;
   constexpr int P = Tr::planes;
   constexpr int WAVES_N = BN / WN;
-  constexpr int NWG = (BM / WM) * WAVES_N;    // waves per K group
-  constexpr int NW = KG * NWG;
+  constexpr int NW = (BM / WM) * WAVES_N;
   constexpr int SEGB = 64;                    // K bytes per row per stage
   constexpr int ROWS = BM + BN;
   constexpr int PLANEB = ROWS * SEGB;         // bytes per plane per stage
-  constexpr int STAGEB = P * PLANEB;
-  constexpr int NINS = P * ROWS / 16;         // 16-row load instructions per stage
-  constexpr int IPI = G * NINS / NW;          // load instructions per wave per barrier interval
+  constexpr int NINS = P * ROWS / 16;         // 1 KB copy instructions per stage
+  constexpr int IPI = NINS / NW;              // copy instructions per wave per stage
   constexpr int FM = WM / 16, FN = WN / 16;
-  static_assert((G * NINS) % NW == 0 && BM % 16 == 0 && BN % 16 == 0, "tile/waves");
-  static_assert(G >= 1 && NS >= 2 * G && NS % G == 0 && G % KG == 0, "stages per barrier");
+  static_assert(NINS % NW == 0 && BM % 16 == 0 && BN % 16 == 0, "tile/waves");
 
   const int tid = threadIdx.x;
   const int lane = tid & 63;
-  const int wave = tid >> 6;
-  const int grp = wave / NWG;
-  const int wig = wave - grp * NWG;
-  const int wm = wig / WAVES_N;
-  const int wn = wig - wm * WAVES_N;
-  const int ktot = (g.K * Tr::esize + SEGB - 1) / SEGB;
-  const int kt0 = kz * g.kchunk;
-  const int ktiles = min(ktot - kt0, g.kchunk);   // >= 1 by construction of the split
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int wm = wave / WAVES_N;
+  const int wn = wave - wm * WAVES_N;
 
-  // This wave's load instructions for one barrier interval: stage offset
-  // (0..G-1), global source of its lane, LDS offset inside a stage.
+  // This wave's copy instructions for one stage: wave-uniform global source
+  // (stage kt0; lane L adds 16 L) and LDS offset inside a buffer.
   const unsigned char* src[IPI];
-  int dst[IPI], sof[IPI];
+  int dst[IPI];
+  const int voff = lane * 16;
   {
     const long nseg_a = g.lda * Tr::esize / SEGB;   // K blocks per 16-row block of A
     const long nseg_b = g.ldb * Tr::esize / SEGB;
 #pragma unroll
     for (int i = 0; i < IPI; ++i) {
       const int q = wave + NW * i;
-      const int gg = q / NINS;
-      const int r = q - gg * NINS;
-      const int p = r / (ROWS / 16);
-      const int rg = r - p * (ROWS / 16);
+      const int p = q / (ROWS / 16);
+      const int rg = q - p * (ROWS / 16);
       const unsigned char* base;
       if (rg < BM / 16)
-        base = static_cast<const unsigned char*>(g.a[p]) + ((long)(tm * (BM / 16) + rg) * nseg_a + kt0) * 1024;
+        base = static_cast<const unsigned char*>(p == 0 ? g.a[0] : g.a[1]) +
+               ((long)(tm * (BM / 16) + rg) * nseg_a + kt0) * 1024;
       else
-        base = static_cast<const unsigned char*>(g.b[p]) +
+        base = static_cast<const unsigned char*>(p == 0 ? g.b[0] : g.b[1]) +
                ((long)(tn * (BN / 16) + rg - BM / 16) * nseg_b + kt0) * 1024;
-      src[i] = base + lane * 16;
+      src[i] = base;
       dst[i] = p * PLANEB + rg * 16 * SEGB;
-      sof[i] = gg;
     }
   }
 
-  // issue the G stages [J G, J G + G) into their ring buffers (indices past
-  // the end are clamped; the re-read lands in a buffer never consumed again)
-#define SF_ISSUE_GROUP(J)                                                                            \
+  // copies of stage ST into buffer BUF (a stage past the end re-reads the
+  // last one into a buffer that is never consumed)
+#define SF_ISSUE(BUF, ST)                                                                            \
   {                                                                                                  \
+    const long st_ = (long)min((ST), ktiles - 1) * 1024;                                             \
     _Pragma("unroll") for (int i_ = 0; i_ < IPI; ++i_) {                                             \
-      const int st_ = (J) * G + sof[i_];                                                             \
-      __builtin_amdgcn_global_load_lds(                                                              \
-          (const void __attribute__((address_space(1)))*)(src[i_] + (long)min(st_, ktiles - 1) * 1024), \
-          (void __attribute__((address_space(3)))*)(lds + (st_ % NS) * STAGEB + dst[i_]), 16, 0, 0); \
+      __builtin_amdgcn_global_load_lds((const void __attribute__((address_space(1)))*)(src[i_] + st_ + voff), \
+                                       (void __attribute__((address_space(3)))*)((BUF) + dst[i_]), 16, 0, 0); \
     }                                                                                                \
   }
+  // MFMAs of one stage from buffer BUF: block i of this wave's A rows and
+  // block j of its B rows, byte 16 lane of each 1 KB block.  The B
+  // fragments stay in registers for the stage; the A fragments of block
+  // row i + 1 are read while the MFMAs of row i run (scheduling barriers keep
+  // the compiler from hoisting more reads than registers allow).
+#define SF_LD(PTR) (*reinterpret_cast<const uint4*>(PTR))
+#define SF_STAGE(BUF)                                                                                \
+  {                                                                                                  \
+    const unsigned char* sb_ = (BUF);                                                                \
+    uint4 fb_[FN][P], fa_[2][P];                                                                     \
+    _Pragma("unroll") for (int j = 0; j < FN; ++j)                                                   \
+      _Pragma("unroll") for (int p = 0; p < P; ++p) fb_[j][p] = SF_LD(sb_ + p * PLANEB + b_off + j * 1024); \
+    _Pragma("unroll") for (int p = 0; p < P; ++p) fa_[0][p] = SF_LD(sb_ + p * PLANEB + a_off);      \
+    _Pragma("unroll") for (int i = 0; i < FM; ++i) {                                                 \
+      if (i + 1 < FM) {                                                                              \
+        _Pragma("unroll") for (int p = 0; p < P; ++p)                                                \
+          fa_[(i + 1) & 1][p] = SF_LD(sb_ + p * PLANEB + a_off + (i + 1) * 1024);                   \
+      }                                                                                              \
+      _Pragma("unroll") for (int j = 0; j < FN; ++j) mma_chunk<MODE>(acc[i][j], fa_[i & 1], fb_[j]); \
+      __builtin_amdgcn_sched_barrier(0);                                                             \
+    }                                                                                                \
+  }
+#define SF_TOP()                                                                                     \
+  __builtin_amdgcn_s_waitcnt(vmcnt_imm<0>());                                                        \
+  __builtin_amdgcn_s_barrier();                                                                      \
+  asm volatile("" ::: "memory");
 
   AccT acc[FM][FN];
 #pragma unroll
@@ -316,75 +200,26 @@ __device__ __forceinline__ void gemm_tile(unsigned char* lds, const GemmArgs& g,
 #pragma unroll
     for (int j = 0; j < FN; ++j) acc[i][j] = AccT{0, 0, 0, 0};
 
-  // fragment reads: 16-row block i of this wave's rows, byte 16 lane of it
   const int a_off = wm * WM * SEGB + lane * 16;
   const int b_off = (BM + wn * WN) * SEGB + lane * 16;
 
-  // Loads run NS - G stages ahead of the first stage consumed; at the top of
-  // an interval NS - 2G stages may remain in flight.
-  constexpr int AHEAD = (NS - G) / G;
-#pragma unroll
-  for (int j = 0; j < AHEAD; ++j) SF_ISSUE_GROUP(j);
-
-  const int iters = (ktiles + G - 1) / G;
-  for (int it = 0; it < iters; ++it) {
-    __builtin_amdgcn_s_waitcnt(vmcnt_imm<(AHEAD - 1) * IPI>());
-    __builtin_amdgcn_s_barrier();
-    asm volatile("" ::: "memory");
-    SF_ISSUE_GROUP(it + AHEAD);
-#pragma unroll
-    for (int gg = 0; gg < G; ++gg) {
-      if (KG > 1 && (gg % KG) != grp) continue;
-      const int kt = it * G + gg;
-      if (G > 1 && kt >= ktiles) break;
-      const unsigned char* sbase = lds + (kt % NS) * STAGEB;
-      uint4 fa[FM][P], fb[FN][P];
-      {
-        unsigned ra[P], rb[P];
-#pragma unroll
-        for (int p = 0; p < P; ++p) {
-          ra[p] = lds_addr(sbase + p * PLANEB + a_off);
-          rb[p] = lds_addr(sbase + p * PLANEB + b_off);
-        }
-        FragLoad<P, FM, FN>::run(fa, fb, ra, rb);
-      }
-#pragma unroll
-      for (int i = 0; i < FM; ++i)
-#pragma unroll
-        for (int j = 0; j < FN; ++j) mma_chunk<MODE>(acc[i][j], fa[i], fb[j]);
-    }
-    asm volatile("" ::: "memory");
+  // ktiles is even (gemm_kstages, plan_gemm), so both buffers are used
+  // once per trip and the accumulators stay in place
+  SF_ISSUE(lds0, 0);
+  for (int kt = 0; kt < ktiles; kt += 2) {
+    SF_TOP();
+    SF_ISSUE(lds1, kt + 1);
+    SF_STAGE(lds0);
+    SF_TOP();
+    SF_ISSUE(lds0, kt + 2);
+    SF_STAGE(lds1);
   }
+  // no copy may still target this workgroup's LDS when it exits
   __builtin_amdgcn_s_waitcnt(vmcnt_imm<0>());
-#undef SF_ISSUE_GROUP
-
-  if constexpr (KG > 1) {
-    // groups 1.. hand their partial sums to group 0 through LDS (fixed order)
-    Acc* red = reinterpret_cast<Acc*>(lds);
-    __builtin_amdgcn_s_barrier();
-    asm volatile("" ::: "memory");
-    for (int q = 1; q < KG; ++q) {
-      if (grp == q) {
-#pragma unroll
-        for (int i = 0; i < FM; ++i)
-#pragma unroll
-          for (int j = 0; j < FN; ++j)
-#pragma unroll
-            for (int t = 0; t < 4; ++t) red[(((wig * FM + i) * FN + j) * 4 + t) * 64 + lane] = acc[i][j][t];
-      }
-      __syncthreads();
-      if (grp == 0) {
-#pragma unroll
-        for (int i = 0; i < FM; ++i)
-#pragma unroll
-          for (int j = 0; j < FN; ++j)
-#pragma unroll
-            for (int t = 0; t < 4; ++t) acc[i][j][t] += red[(((wig * FM + i) * FN + j) * 4 + t) * 64 + lane];
-      }
-      __syncthreads();
-    }
-    if (grp != 0) return;
-  }
+#undef SF_ISSUE
+#undef SF_STAGE
+#undef SF_LD
+#undef SF_TOP
 
   // epilogue
   constexpr int RSTEP = (MODE == M_F64) ? 4 : 1;          // row stride between accumulator registers
@@ -403,58 +238,40 @@ __device__ __forceinline__ void gemm_tile(unsigned char* lds, const GemmArgs& g,
     }
 }
 
-// Tile configurations.  TileL (128 x 128, 8 waves of 64 x 32, two 64 KB
-// LDS stages for bf16x3) is the single-image shape; TileS (64 x 64, 4 waves
-// of 32 x 32) serves small images in the batched form.
-#ifndef SF_TILE_BM
-#define SF_TILE_BM 128
-#define SF_TILE_BN 128
-#define SF_TILE_WM 64
-#define SF_TILE_WN 32
-#define SF_TILE_NS 2
-#endif
-#ifndef SF_TILE_G
-#define SF_TILE_G 1
-#endif
-#ifndef SF_TILE_KG
-#define SF_TILE_KG 1
-#endif
-template <int BM_, int BN_, int WM_, int WN_, int NS_, int G_, int KG_>
+// Tile configurations.  Tile256 (256 x 256, 8 waves of 128 x 64, two 64 KB
+// LDS stages for bf16x3, one workgroup per CU) is the single-image shape of
+// the 2-byte and FP32 modes; FP64 accumulators (8 registers per 16 x 16
+// block) need the smaller Tile128.  TileS (64 x 64, 4 waves of 32 x 32)
+// serves small images in the batched form.
+template <int BM_, int BN_, int WM_, int WN_>
 struct Tile {
   static constexpr int BM = BM_, BN = BN_, WM = WM_, WN = WN_;
-  static constexpr int NS = NS_;   // LDS pipeline stages of 64 K-bytes
-  static constexpr int G = G_;     // stages consumed per barrier
-  static constexpr int KG = KG_;   // K groups of waves inside a workgroup
-  static constexpr int THREADS = KG * (BM / WM) * (BN / WN) * 64;
+  static constexpr int THREADS = (BM / WM) * (BN / WN) * 64;
+  // bytes of one of the two LDS stage buffers
   template <int MODE>
-  static constexpr int lds_bytes() {
-    using Acc = typename ModeTraits<MODE>::Acc;
-    constexpr int stages = NS * ModeTraits<MODE>::planes * (BM + BN) * 64;
-    constexpr int red = KG > 1 ? BM * BN * (int)sizeof(Acc) : 0;
-    return stages > red ? stages : red;
-  }
+  static constexpr int buf_bytes() { return ModeTraits<MODE>::planes * (BM + BN) * 64; }
 };
-using TileL = Tile<SF_TILE_BM, SF_TILE_BN, SF_TILE_WM, SF_TILE_WN, SF_TILE_NS, SF_TILE_G, SF_TILE_KG>;
-using TileS = Tile<64, 64, 32, 32, 4, 1, 1>;
+#ifdef SF_TILE_BM
+using Tile256 = Tile<SF_TILE_BM, SF_TILE_BN, SF_TILE_WM, SF_TILE_WN>;
+#else
+using Tile256 = Tile<256, 256, 128, 64>;
+#endif
+using Tile128 = Tile<128, 128, 64, 32>;
+using TileS = Tile<64, 64, 32, 32>;
+
+template <int MODE> struct BigTile { using T = Tile256; };
+template <> struct BigTile<M_F64> { using T = Tile128; };
 
 struct TileCfg {
   static constexpr int ROW_PAD = 256;     // operand row allocations are multiples of this
   static constexpr int K_PAD = 64;        // operand leading dimensions are multiples of this
-  static_assert(TileL::BM <= ROW_PAD && TileL::BN <= ROW_PAD, "row padding must cover a tile");
+  static_assert(Tile256::BM <= ROW_PAD && Tile256::BN <= ROW_PAD, "row padding must cover a tile");
 };
 
-template <int MODE, class T = TileL>
-constexpr size_t gemm_lds_bytes() { return (size_t)T::template lds_bytes<MODE>(); }
-
-template <int MODE, class T, class Epi>
-__global__ __launch_bounds__(T::THREADS, 1) void gemm_nt_kernel(GemmArgs g, Epi epi) {
-  __shared__ __attribute__((aligned(16))) unsigned char lds[T::template lds_bytes<MODE>()];
-  const int tiles_m = (g.M + T::BM - 1) / T::BM;
-  const int tiles_n = (g.N + T::BN - 1) / T::BN;
-  int tm, tn;
-  map_tile(blockIdx.x, gridDim.x, tiles_m, tiles_n, tm, tn);
-  gemm_tile<MODE, T>(lds, g, tm, tn, blockIdx.y, epi);
-}
+// K stages of 64 bytes, rounded up to an even count: the K padding of the
+// operands (a multiple of 64 elements, zero-filled) always covers it.
+template <int MODE>
+__host__ __device__ inline int gemm_kstages(int K) { return 2 * ((K * ModeTraits<MODE>::esize + 127) / 128); }
 
 // One tile of one product of a batch: the product index selects the GEMM
 // arguments and the epilogue parameters.
@@ -467,75 +284,160 @@ struct WorkItem {
 template <int MODE, class T, class Epi>
 __global__ __launch_bounds__(T::THREADS, 1) void gemm_grouped_kernel(const GemmArgs* args, const Epi* epis,
                                                                      const WorkItem* work) {
-  __shared__ __attribute__((aligned(16))) unsigned char lds[T::template lds_bytes<MODE>()];
+  __shared__ __attribute__((aligned(16))) unsigned char lds0[T::template buf_bytes<MODE>()];
+  __shared__ __attribute__((aligned(16))) unsigned char lds1[T::template buf_bytes<MODE>()];
   int bid = blockIdx.x;
   if ((gridDim.x & 7) == 0) bid = (bid & 7) * (gridDim.x >> 3) + (bid >> 3);
   const WorkItem w = work[bid];
-  const GemmArgs g = args[w.prod];
-  const Epi e = epis[w.prod];
-  gemm_tile<MODE, T>(lds, g, w.tm, w.tn, 0, e);
+  // the arguments stay in global memory (uniform scalar loads); a private
+  // copy would put their small arrays in scratch
+  const GemmArgs& g = args[w.prod];
+  const Epi& e = epis[w.prod];
+  gemm_tile<MODE, T>(lds0, lds1, g, w.tm, w.tn, 0, gemm_kstages<MODE>(g.K), e);
 }
 
-// Partial product of one K split, stored for the reduction.
-template <int MODE>
-struct EpiPartial {
-  typename ModeTraits<MODE>::Acc* ws;
-  int M, N;
-  __device__ __forceinline__ void operator()(int row, int col, typename ModeTraits<MODE>::Acc v) const {
-    ws[((long)blockIdx.y * M + row) * N + col] = v;
+// ------------------------------------------------------------ planned launch
+// A single product runs from a work list built on the host (plan_gemm): item
+// i is workgroup i's tile, either over the whole K range (the GEMM's own
+// epilogue runs) or over one of S K-splits (the partial goes to a per-tile
+// workspace slot and tile_reduce_kernel adds the splits in order and runs the
+// epilogue).  Workgroups are dispatched round-robin over the XCDs (id % 8), so
+// the list interleaves eight per-XCD sequences, each a compact block of tiles
+// over one K range, sharing that XCD's L2.
+struct PlanItem {
+  int tm, tn;
+  int z;      // K split, or -1 for the whole K range
+  int slot;   // workspace slot of a split tile
+};
+
+template <class Acc>
+struct EpiSlot {
+  Acc* ws;      // BM x BN partial of this (tile, split)
+  int r0, c0, bn;
+  __device__ __forceinline__ void operator()(int row, int col, Acc v) const {
+    ws[(long)(row - r0) * bn + (col - c0)] = v;
   }
 };
 
-// Sums the K-split partials in split order (deterministic) and applies the
-// GEMM's own epilogue element-wise.
-template <class Acc, class Epi>
-__global__ void splitk_reduce_kernel(const Acc* ws, int S, int M, int N, Epi epi) {
-  const long total = (long)M * N;
-  for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < total; e += (long)gridDim.x * blockDim.x) {
-    Acc v = ws[e];
-    for (int z = 1; z < S; ++z) v += ws[z * total + e];
-    const int row = (int)(e / N);
-    epi(row, (int)(e - (long)row * N), v);
+template <int MODE, class T, class Epi>
+__global__ __launch_bounds__(T::THREADS, 1) void gemm_planned_kernel(GemmArgs g, Epi epi,
+                                                                     typename ModeTraits<MODE>::Acc* ws, int S,
+                                                                     const PlanItem* work) {
+  __shared__ __attribute__((aligned(16))) unsigned char lds0[T::template buf_bytes<MODE>()];
+  __shared__ __attribute__((aligned(16))) unsigned char lds1[T::template buf_bytes<MODE>()];
+  const PlanItem w = work[blockIdx.x];
+  const int ktot = gemm_kstages<MODE>(g.K);
+  if (w.z < 0) {
+    gemm_tile<MODE, T>(lds0, lds1, g, w.tm, w.tn, 0, ktot, epi);
+  } else {
+    const int kt0 = w.z * g.kchunk;
+    EpiSlot<typename ModeTraits<MODE>::Acc> part{ws + (long)(w.slot * S + w.z) * (T::BM * T::BN), w.tm * T::BM,
+                                                 w.tn * T::BN, T::BN};
+    gemm_tile<MODE, T>(lds0, lds1, g, w.tm, w.tn, kt0, min(ktot - kt0, g.kchunk), part);
   }
 }
 
-template <int MODE>
-inline int gemm_kstages(int K) { return (K * ModeTraits<MODE>::esize + 63) / 64; }
+// Adds the S partials of every split tile in split order (deterministic) and
+// applies the product's epilogue.  Block x handles split tile x.
+template <class Acc, class Epi, int BM, int BN>
+__global__ void tile_reduce_kernel(const Acc* ws, int S, int M, int N, const int2* tiles, Epi epi) {
+  const int2 t = tiles[blockIdx.x];
+  const Acc* base = ws + (long)blockIdx.x * S * (BM * BN);
+  for (int e = blockIdx.y * blockDim.x + threadIdx.x; e < BM * BN; e += gridDim.y * blockDim.x) {
+    const int lr = e / BN, lc = e - lr * BN;
+    const int row = t.x * BM + lr, col = t.y * BN + lc;
+    if (row < M && col < N) {
+      Acc v = base[e];
+      for (int z = 1; z < S; ++z) v += base[(long)z * (BM * BN) + e];
+      epi(row, col, v);
+    }
+  }
+}
 
-// Number of K splits for an M x N x K product: enough workgroups to fill
-// `slots` (CUs x resident blocks per CU), keeping at least 16 K stages per split.
-template <int MODE>
-inline int choose_splitk(int M, int N, int K, int slots) {
-  const int tiles = ((M + TileL::BM - 1) / TileL::BM) * ((N + TileL::BN - 1) / TileL::BN);
-  const int kst = gemm_kstages<MODE>(K);
+// Host-side plan of one product shape.
+struct GemmPlan {
+  std::vector<PlanItem> items;     // in workgroup order
+  std::vector<int2> split_tiles;   // (tm, tn) per workspace slot
+  int S = 1;                       // K splits of the split tiles
+  int kchunk = 0;                  // K stages per split
+  size_t ws_elems() const { return split_tiles.size() * (size_t)S; }   // x BM x BN accumulator values
+};
+
+// Full tiles fill whole rounds of `slots` resident workgroups; the tiles of
+// a last, partial round are split along K so that they fill one more round
+// (at least 4 K stages per split).  Inside a round, tiles are taken in groups
+// of 8 tile rows walked column by column, and consecutive runs of that order
+// go to the same XCD.
+template <class T>
+GemmPlan plan_gemm(int M, int N, int kst, int slots) {
+  GemmPlan pl;
+  const int tiles_m = (M + T::BM - 1) / T::BM, tiles_n = (N + T::BN - 1) / T::BN;
+  constexpr int GROUP_M = 8;
+  std::vector<int2> order;
+  for (int g0 = 0; g0 < tiles_m; g0 += GROUP_M)
+    for (int tn = 0; tn < tiles_n; ++tn)
+      for (int tm = g0; tm < std::min(tiles_m, g0 + GROUP_M); ++tm) order.push_back(make_int2(tm, tn));
+  const int tiles = (int)order.size();
+  const int full = slots > 0 ? (tiles / slots) * slots : tiles;
+  const int tail = tiles - full;
   int S = 1;
-  while (S < 16 && tiles * S * 2 <= slots && kst / (S * 2) >= 16) S *= 2;
-  return S;
+  if (tail > 0)
+    while (S < 16 && tail * S * 2 <= slots && kst / (S * 2) >= 4) S *= 2;
+  pl.kchunk = 2 * ((kst + 2 * S - 1) / (2 * S));   // even, like kst
+  S = (kst + pl.kchunk - 1) / pl.kchunk;           // every split non-empty
+  pl.S = S;
+  auto place = [&](const std::vector<PlanItem>& ph) {
+    const int n = (int)ph.size();
+    if (n % 8 != 0) {
+      pl.items.insert(pl.items.end(), ph.begin(), ph.end());
+      return;
+    }
+    const int per = n / 8;
+    const size_t base = pl.items.size();
+    pl.items.resize(base + n);
+    for (int x = 0; x < 8; ++x)
+      for (int j = 0; j < per; ++j) pl.items[base + (size_t)8 * j + x] = ph[(size_t)x * per + j];
+  };
+  for (int r0 = 0; r0 < full; r0 += slots) {
+    std::vector<PlanItem> ph;
+    for (int i = r0; i < r0 + slots; ++i) ph.push_back(PlanItem{order[i].x, order[i].y, -1, 0});
+    place(ph);
+  }
+  if (tail > 0) {
+    std::vector<PlanItem> ph;
+    if (S == 1) {
+      for (int i = full; i < tiles; ++i) ph.push_back(PlanItem{order[i].x, order[i].y, -1, 0});
+    } else {
+      for (int i = full; i < tiles; ++i) pl.split_tiles.push_back(order[i]);
+      for (int z = 0; z < S; ++z)
+        for (int i = full; i < tiles; ++i) ph.push_back(PlanItem{order[i].x, order[i].y, z, i - full});
+    }
+    place(ph);
+  }
+  return pl;
 }
 
-// Launch; with S > 1 the partials go to `ws` (S x M x N accumulator values)
-// and the reduction applies `epi`.
+// Device copy of a plan (arrays owned by the caller's arena).
+struct GemmPlanDev {
+  const PlanItem* items = nullptr;
+  const int2* split_tiles = nullptr;
+  int nitems = 0, nsplit = 0, S = 1, kchunk = 0;
+};
+
+// Launch of a planned product: the tile pass, then (with split tiles) the
+// reduction that applies `epi`.  `ws` holds nsplit x S x BM x BN values.
 template <int MODE, class Epi>
-hipError_t launch_gemm(GemmArgs g, const Epi& epi, hipStream_t s, int S = 1,
-                       typename ModeTraits<MODE>::Acc* ws = nullptr) {
-  using T = TileL;
-  if (g.M <= 0 || g.N <= 0) return hipSuccess;
-  const int tiles = ((g.M + T::BM - 1) / T::BM) * ((g.N + T::BN - 1) / T::BN);
-  constexpr int threads = T::THREADS;
-  const int kst = gemm_kstages<MODE>(g.K);
-  if (S <= 1 || !ws) {
-    g.kchunk = kst;
-    hipLaunchKernelGGL((gemm_nt_kernel<MODE, T, Epi>), dim3(tiles),
-                       dim3(threads), 0, s, g, epi);
-    return hipGetLastError();
-  }
-  g.kchunk = (kst + S - 1) / S;
-  S = (kst + g.kchunk - 1) / g.kchunk;   // every split non-empty
-  EpiPartial<MODE> part{ws, g.M, g.N};
-  hipLaunchKernelGGL((gemm_nt_kernel<MODE, T, EpiPartial<MODE>>),
-                     dim3(tiles, S), dim3(threads), 0, s, g, part);
-  hipLaunchKernelGGL((splitk_reduce_kernel<typename ModeTraits<MODE>::Acc, Epi>), dim3(2048), dim3(256), 0, s,
-                     ws, S, g.M, g.N, epi);
+hipError_t launch_planned(GemmArgs g, const Epi& epi, const GemmPlanDev& pl, typename ModeTraits<MODE>::Acc* ws,
+                          hipStream_t s) {
+  using T = typename BigTile<MODE>::T;
+  using Acc = typename ModeTraits<MODE>::Acc;
+  if (g.M <= 0 || g.N <= 0 || pl.nitems == 0) return hipSuccess;
+  g.kchunk = pl.kchunk;
+  hipLaunchKernelGGL((gemm_planned_kernel<MODE, T, Epi>), dim3(pl.nitems), dim3(T::THREADS), 0, s, g, epi, ws,
+                     pl.S, pl.items);
+  if (pl.nsplit > 0)
+    hipLaunchKernelGGL((tile_reduce_kernel<Acc, Epi, T::BM, T::BN>), dim3(pl.nsplit, 16), dim3(256), 0, s, ws,
+                       pl.S, g.M, g.N, pl.split_tiles, epi);
   return hipGetLastError();
 }
 

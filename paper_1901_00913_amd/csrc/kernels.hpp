@@ -313,7 +313,9 @@ struct EpiUpdateSeq {
   const int* counter;
   __device__ __forceinline__ void operator()(int i, int j, Acc g) const {
     const int k = *counter + 1;
-    update_point<MODE, KIND>(y, op_index<MODE>(i, j, ldy), st[(k - 1) & 1], st[k & 1], (long)i * n + j, g, c1, c2,
+    void* const x1 = (k & 1) ? st[0] : st[1];   // st[(k - 1) & 1], selected without indexing
+    void* const x2 = (k & 1) ? st[1] : st[0];   // st[k & 1]
+    update_point<MODE, KIND>(y, op_index<MODE>(i, j, ldy), x1, x2, (long)i * n + j, g, c1, c2,
                              beta[k - 1], beta[k], nonneg);
   }
 };

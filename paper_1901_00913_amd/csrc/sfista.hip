@@ -30,8 +30,8 @@ struct sfista_plan {
   void* st[2] = {};
   double* aux = nullptr;      // m x n FP64 scratch (power iterate, copies)
   double* red = nullptr;      // reduction partials [RED_BLOCKS] + scalars
-  void* ws = nullptr;         // K-split partials of F2 and G2
-  int split_f2 = 1, split_g2 = 1;
+  void* ws = nullptr;         // K-split partials of the planned products
+  GemmPlanDev pl[4];          // work lists of F1, F2, G1, G2
   double bobs_norm = 0.0;
   // optional per-GEMM event timing
   int timing = 0;
@@ -110,12 +110,29 @@ GemmArgs gargs(void* const* a, long lda, void* const* b, long ldb, int M, int N,
   return g;
 }
 
+template <int MODE>
+typename ModeTraits<MODE>::Acc* ws_of(sfista_plan* h) {
+  return static_cast<typename ModeTraits<MODE>::Acc*>(h->ws);
+}
+
+// Workgroups of the planned GEMM kernel resident per CU.
+template <int MODE>
+int resident_per_cu() {
+  using T = typename BigTile<MODE>::T;
+  int nb = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, gemm_planned_kernel<MODE, T, EpiStack<MODE>>, T::THREADS, 0) !=
+          hipSuccess || nb < 1)
+    nb = 1;
+  return nb;
+}
+
 // F1: T_k = Y A_k^T for all k, stored as T^T (n x rm):  Tt[j][k m + i].
 template <int MODE>
 hipError_t run_f1(sfista_plan* h, void* const* y, long ldy) {
   EpiStack<MODE> e;
   e.out[0] = h->T[0]; e.out[1] = h->T[1]; e.ldo = h->ldT; e.D = h->n; e.colblk = h->m;
-  return launch_gemm<MODE>(gargs<MODE>(h->W, h->ldW, y, ldy, h->r * h->n, h->m, h->n), e, h->s);
+  return launch_planned<MODE>(gargs<MODE>(h->W, h->ldW, y, ldy, h->r * h->n, h->m, h->n), e, h->pl[0], ws_of<MODE>(h),
+                              h->s);
 }
 
 // F2: R^T = (sum_k B_k T_k)^T - Bobs^T   (bobs optional)
@@ -125,8 +142,8 @@ hipError_t run_f2(sfista_plan* h, bool with_bobs, double* copy) {
   e.out[0] = h->R[0]; e.out[1] = h->R[1]; e.ldo = h->ldR;
   e.bobs_t = with_bobs ? static_cast<const typename ModeTraits<MODE>::Acc*>(h->bobs_t) : nullptr;
   e.m = h->m; e.copy = copy; e.n = h->n;
-  return launch_gemm<MODE>(gargs<MODE>(h->T, h->ldT, h->Bc, h->ldBc, h->n, h->m, h->r * h->m), e, h->s,
-                           h->split_f2, static_cast<typename ModeTraits<MODE>::Acc*>(h->ws));
+  return launch_planned<MODE>(gargs<MODE>(h->T, h->ldT, h->Bc, h->ldBc, h->n, h->m, h->r * h->m), e, h->pl[1],
+                              ws_of<MODE>(h), h->s);
 }
 
 // G1: S_k = B_k^T R for all k, stored side by side (m x rn): S[i][k n + j].
@@ -134,14 +151,15 @@ template <int MODE>
 hipError_t run_g1(sfista_plan* h) {
   EpiStack<MODE> e;
   e.out[0] = h->S[0]; e.out[1] = h->S[1]; e.ldo = h->ldS; e.D = h->m; e.colblk = h->n;
-  return launch_gemm<MODE>(gargs<MODE>(h->Bt, h->ldBt, h->R, h->ldR, h->r * h->m, h->n, h->m), e, h->s);
+  return launch_planned<MODE>(gargs<MODE>(h->Bt, h->ldBt, h->R, h->ldR, h->r * h->m, h->n, h->m), e, h->pl[2],
+                              ws_of<MODE>(h), h->s);
 }
 
 // G2 with an arbitrary epilogue: sum_k S_k A_k.
 template <int MODE, class Epi>
 hipError_t run_g2(sfista_plan* h, const Epi& e) {
-  return launch_gemm<MODE>(gargs<MODE>(h->S, h->ldS, h->At, h->ldAt, h->m, h->n, h->r * h->n), e, h->s,
-                           h->split_g2, static_cast<typename ModeTraits<MODE>::Acc*>(h->ws));
+  return launch_planned<MODE>(gargs<MODE>(h->S, h->ldS, h->At, h->ldAt, h->m, h->n, h->r * h->n), e, h->pl[3],
+                              ws_of<MODE>(h), h->s);
 }
 
 template <int MODE>
@@ -254,18 +272,42 @@ int setup_mode(sfista_plan* h, const double* Bobs, const double* A, const double
        (h->red = static_cast<double*>(h->arena.alloc_zero((RED_BLOCKS + 8) * 8, h->s)));
   if (!ok) return set_error(SFISTA_ERR_NOMEM, "device allocation failed (%s)", h->arena.last_error());
 
-  // K splits for the two square products (their tile count alone can leave CUs idle)
+  // work lists of the four products (tile order, K splits of the last round)
   {
+    using TB = typename BigTile<MODE>::T;
     int dev = 0, cus = 256;
     if (hipGetDevice(&dev) == hipSuccess) {
       hipDeviceProp_t prop;
       if (hipGetDeviceProperties(&prop, dev) == hipSuccess) cus = prop.multiProcessorCount;
     }
-    const int per_cu = (int)(160 * 1024 / gemm_lds_bytes<MODE>()) > 1 ? 2 : 1;
-    h->split_f2 = choose_splitk<MODE>(n, m, (int)rm, cus * per_cu);
-    h->split_g2 = choose_splitk<MODE>(m, n, (int)rn, cus * per_cu);
-    const int smax = h->split_f2 > h->split_g2 ? h->split_f2 : h->split_g2;
-    if (smax > 1 && !(h->ws = h->arena.alloc_zero((size_t)smax * m * n * sizeof(Acc), h->s)))
+    const int slots = cus * resident_per_cu<MODE>();
+    const GemmPlan plans[4] = {
+        plan_gemm<TB>((int)rn, m, gemm_kstages<MODE>(n), slots), plan_gemm<TB>(n, m, gemm_kstages<MODE>((int)rm), slots),
+        plan_gemm<TB>((int)rm, n, gemm_kstages<MODE>(m), slots), plan_gemm<TB>(m, n, gemm_kstages<MODE>((int)rn), slots)};
+    size_t ws_elems = 0;
+    for (int q = 0; q < 4; ++q) {
+      const GemmPlan& gp = plans[q];
+      GemmPlanDev& pd = h->pl[q];
+      PlanItem* items = static_cast<PlanItem*>(h->arena.alloc_zero(gp.items.size() * sizeof(PlanItem), h->s));
+      int2* tiles = gp.split_tiles.empty()
+                        ? nullptr
+                        : static_cast<int2*>(h->arena.alloc_zero(gp.split_tiles.size() * sizeof(int2), h->s));
+      if (!items || (!gp.split_tiles.empty() && !tiles))
+        return set_error(SFISTA_ERR_NOMEM, "device allocation failed (%s)", h->arena.last_error());
+      if (hipMemcpyAsync(items, gp.items.data(), gp.items.size() * sizeof(PlanItem), hipMemcpyHostToDevice, h->s) !=
+              hipSuccess ||
+          (tiles && hipMemcpyAsync(tiles, gp.split_tiles.data(), gp.split_tiles.size() * sizeof(int2),
+                                   hipMemcpyHostToDevice, h->s) != hipSuccess))
+        return set_error(SFISTA_ERR_HIP, "plan upload failed");
+      pd.items = items;
+      pd.split_tiles = tiles;
+      pd.nitems = (int)gp.items.size();
+      pd.nsplit = (int)gp.split_tiles.size();
+      pd.S = gp.S;
+      pd.kchunk = gp.kchunk;
+      ws_elems = std::max(ws_elems, gp.ws_elems() * TB::BM * TB::BN);
+    }
+    if (ws_elems > 0 && !(h->ws = h->arena.alloc_zero(ws_elems * sizeof(Acc), h->s)))
       return set_error(SFISTA_ERR_NOMEM, "device allocation failed (%s)", h->arena.last_error());
   }
 
@@ -539,7 +581,7 @@ struct sfista_batch {
   void* depi[4] = {};               // per product: device array of epilogues
   WorkItem* dwork[4][2] = {};       // per product and tile shape: work list
   int nwork[4][2] = {};
-  int choice[4] = {0, 0, 0, 0};     // 0 = TileL, 1 = TileS
+  int choice[4] = {0, 0, 0, 0};     // 0 = the mode's big tile, 1 = TileS
   double* beta = nullptr;           // beta[k] = (t_k - 1) / t_{k+1}, beta[0] = 0
   int* counter = nullptr;           // iterations completed (device)
   hipGraphExec_t gexec = nullptr;
@@ -571,7 +613,8 @@ hipError_t launch_grouped(sfista_batch* b, int prod) {
 
 template <int MODE, class Epi>
 hipError_t launch_product(sfista_batch* b, int prod) {
-  return b->choice[prod] ? launch_grouped<MODE, TileS, Epi>(b, prod) : launch_grouped<MODE, TileL, Epi>(b, prod);
+  return b->choice[prod] ? launch_grouped<MODE, TileS, Epi>(b, prod)
+                         : launch_grouped<MODE, typename BigTile<MODE>::T, Epi>(b, prod);
 }
 
 template <int MODE, int KIND>
@@ -646,7 +689,8 @@ int batch_build(sfista_batch* b) {
     for (int i = 0; i < cnt; ++i) order[i] = i;
     std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return args[q][x].K > args[q][y].K; });
     for (int c = 0; c < 2; ++c) {
-      const int BM = c ? TileS::BM : TileL::BM, BN = c ? TileS::BN : TileL::BN;
+      using TB = typename BigTile<MODE>::T;
+      const int BM = c ? TileS::BM : TB::BM, BN = c ? TileS::BN : TB::BN;
       std::vector<WorkItem> w;
       for (int i : order) {
         const int tm_n = (args[q][i].M + BM - 1) / BM, tn_n = (args[q][i].N + BN - 1) / BN;
@@ -741,7 +785,8 @@ int batch_setup_mode(sfista_batch* b) {
   int cus = 256, dev = 0;
   hipDeviceProp_t prop;
   if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess) cus = prop.multiProcessorCount;
-  for (int q = 0; q < 4; ++q) b->choice[q] = b->nwork[q][0] >= 2 * cus ? 0 : 1;
+  const int slots = cus * resident_per_cu<MODE>();
+  for (int q = 0; q < 4; ++q) b->choice[q] = b->nwork[q][0] >= 2 * slots ? 0 : 1;
   if (b->flags & SFISTA_BATCH_AUTOTUNE) {
     const std::string key = batch_key(b);
     if (!tune_cache_lookup(key, b->choice)) {
