@@ -326,6 +326,81 @@ def sfista64(K, H, B, lam, L, iters, X0=None, nonneg=False, history=None):
     return x
 
 
+def sfista64_grad(K, H, B, lam, L, iters, x_true, X0=None):
+    """Unrolled Algorithm 2 as a differentiable map (the differentiable form).
+
+    Runs ``iters`` unconstrained iterations from ``X0`` (zero by default)
+    with ``L`` held fixed, takes the loss ``mean((X_iters - x_true)^2)`` and
+    differentiates it in reverse mode through every step of the iteration:
+
+    * Step 1 written as ``R_k = sum_i H_i Y_k K_i^T - B``,
+      ``G_k = sum_j H_j^T R_k K_j``, ``X_k = (L Y_k - G_k) / (L + lam^2)``;
+    * Step 3 as ``Y_{k+1} = (1 + beta_k) X_k - beta_k X_{k-1}`` with
+      ``beta_k = (t_k - 1) / t_{k+1}`` from Step 2 (data-independent).
+
+    With ``s = L + lam^2`` and adjoints written with a bar, for k = iters..1:
+    ``Xbar_k = [k = iters] dloss/dX + (1 + beta_k) Ybar_{k+1} - beta_{k+1} Ybar_{k+2}``,
+    ``Gbar = -Xbar_k / s``, ``Rbar = sum_j H_j Gbar K_j^T``,
+    ``Ybar_k = (L / s) Xbar_k + sum_i H_i^T Rbar K_i``,
+    ``dH_j += R_k K_j Gbar^T + Rbar K_j Y_k^T``,
+    ``dK_j += R_k^T H_j Gbar + Rbar^T H_j Y_k``,
+    ``dlam += <Xbar_k, -2 lam X_k / s>``.
+
+    Returns ``(loss, dK, dH, dlam)``.  Every iterate is kept (no
+    checkpointing): this is the plain reference.
+    """
+    B = np.asarray(B, dtype=np.float64)
+    K = np.asarray(K, dtype=np.float64)
+    H = np.asarray(H, dtype=np.float64)
+    m, n = B.shape
+    r = K.shape[0]
+    s = L + lam * lam
+    xs = [np.zeros((m, n)) if X0 is None else np.array(X0, dtype=np.float64)]
+    ys, rs, betas = [None], [None], [0.0]
+    y = xs[0].copy()
+    t = 1.0
+    for _ in range(iters):
+        resid = apply_As(K, H, y) - B
+        x = (L * y - apply_AsT(K, H, resid)) / s
+        t_next = momentum(t)
+        beta = (t - 1.0) / t_next
+        ys.append(y)
+        rs.append(resid)
+        betas.append(beta)
+        y = x + beta * (x - xs[-1])
+        xs.append(x)
+        t = t_next
+    X = xs[iters]
+    loss = float(np.mean((X - x_true) ** 2))
+    dK = np.zeros_like(K)
+    dH = np.zeros_like(H)
+    dlam = 0.0
+    ybar1 = np.zeros((m, n))   # Ybar_{k+1}
+    ybar2 = np.zeros((m, n))   # Ybar_{k+2}
+    for k in range(iters, 0, -1):
+        xbar = (1.0 + betas[k]) * ybar1
+        if k + 1 <= iters:
+            xbar = xbar - betas[k + 1] * ybar2
+        if k == iters:
+            xbar = xbar + 2.0 * (X - x_true) / (m * n)
+        gbar = -xbar / s
+        dlam += float(np.sum(xbar * (-2.0 * lam / s) * xs[k]))
+        rbar = apply_As(K, H, gbar)
+        ybar = (L / s) * xbar + apply_AsT(K, H, rbar)
+        for j in range(r):
+            dH[j] += rs[k] @ K[j] @ gbar.T + rbar @ K[j] @ ys[k].T
+            dK[j] += rs[k].T @ H[j] @ gbar + rbar.T @ H[j] @ ys[k]
+        ybar2 = ybar1
+        ybar1 = ybar
+    return loss, dK, dH, dlam
+
+
+def sfista64_loss(K, H, B, lam, L, iters, x_true, X0=None):
+    """The loss of :func:`sfista64_grad` alone (forward only)."""
+    X = sfista64(K, H, B, lam, L, iters, X0=X0)
+    return float(np.mean((X - x_true) ** 2))
+
+
 # --------------------------------------------------------------------------
 # Lipschitz constant and closed forms
 # --------------------------------------------------------------------------
