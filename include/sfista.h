@@ -196,6 +196,48 @@ int sfista_batch_tiles(sfista_batch_handle h, int* choice);
 
 void sfista_batch_destroy(sfista_batch_handle h);
 
+/* ---------------------------------------------------------------------
+ * Differentiable form: the unrolled iteration as a function of the factors
+ * and lambda, and its reverse-mode adjoint.
+ *
+ * The forward pass runs `iters` unconstrained iterations of Algorithm 2 from
+ * X_0 = 0 with L held fixed (a constant of the map, not differentiated) and
+ * keeps (X_{c-1}, X_c) every `ckpt_every` iterations.  The backward pass
+ * takes dX = d(loss)/d(X_iters) and returns the gradient with respect to
+ * every entry of the dense factors A (r x n x n) and B (r x m x m) and to
+ * lambda: it recomputes one checkpoint segment at a time and runs the adjoint
+ * of Step 3 (momentum), of Step 1 (the normal-operator products, reusing the
+ * GEMMs of the forward shapes) and the factor-gradient products
+ *   dB_j += sum_k R_k (G~_k A_j^T)^T + Rbar_k (Y_k A_j^T)^T,
+ *   dA_j += sum_k (B_j^T R_k)^T G~_k + (B_j^T Rbar_k)^T Y_k,
+ * with G~_k = -Xbar_k / (L + lambda^2) and Rbar_k = A_s(G~_k), as two GEMMs
+ * per segment whose K dimension runs over the segment's iterations.
+ *
+ * precision: SFISTA_FP32 (FP32 MFMA, FP32 accumulation) or SFISTA_FP64;
+ * iterates and adjoints are FP64 in both.  Buffers are device memory,
+ * row-major, caller-owned; setup copies what it needs (inputs may be freed
+ * afterwards).  L <= 0 asks for the power estimate (30 steps).  nonneg is
+ * not supported in this form.
+ * --------------------------------------------------------------------- */
+typedef struct sfista_diff* sfista_diff_handle;
+
+int sfista_diff_setup(const double* Bobs, int m, int n, const double* A, const double* B, int r, double lambda,
+                      double L, int precision, int iters, int ckpt_every, hipStream_t stream,
+                      sfista_diff_handle* out);
+
+/* Forward pass: X_out (m x n, FP64, nullable) receives X_iters.  May be
+ * called again (it restarts from X_0). */
+int sfista_diff_forward(sfista_diff_handle h, double* X_out);
+
+/* Backward pass after a forward pass: dX (m x n) in; dA (r x n x n) and dB
+ * (r x m x m) are overwritten with the gradients; *dlambda (host) too. */
+int sfista_diff_backward(sfista_diff_handle h, const double* dX, double* dA, double* dB, double* dlambda);
+
+/* The L in use (given or estimated). */
+int sfista_diff_get_L(sfista_diff_handle h, double* L);
+
+void sfista_diff_destroy(sfista_diff_handle h);
+
 /* Lipschitz constant in use by the plan (estimated or given). */
 int sfista_get_L(sfista_handle h, double* L);
 

@@ -47,6 +47,24 @@ static __global__ __launch_bounds__(RED_THREADS) void sum_partials_kernel(const 
   if (threadIdx.x == 0) *out = t;
 }
 
+// F(e) returns the value itself (a dot product when F multiplies two arrays).
+template <class F>
+__global__ __launch_bounds__(RED_THREADS) void sum_partial_kernel(F f, long count, double* partial) {
+  __shared__ double sh[RED_THREADS / 64];
+  double acc = 0.0;
+  for (long e = blockIdx.x * (long)RED_THREADS + threadIdx.x; e < count; e += (long)RED_BLOCKS * RED_THREADS)
+    acc += f(e);
+  const double t = block_sum(acc, sh);
+  if (threadIdx.x == 0) partial[blockIdx.x] = t;
+}
+
+template <class F>
+hipError_t sumf(F f, long count, double* partial, double* out, hipStream_t s) {
+  hipLaunchKernelGGL(sum_partial_kernel<F>, dim3(RED_BLOCKS), dim3(RED_THREADS), 0, s, f, count, partial);
+  hipLaunchKernelGGL(sum_partials_kernel, dim3(1), dim3(RED_THREADS), 0, s, partial, RED_BLOCKS, out);
+  return hipGetLastError();
+}
+
 template <class F>
 hipError_t sumsq(F f, long count, double* partial, double* out, hipStream_t s) {
   hipLaunchKernelGGL(sumsq_partial_kernel<F>, dim3(RED_BLOCKS), dim3(RED_THREADS), 0, s, f, count, partial);
@@ -90,6 +108,10 @@ struct StateDiffSq {      // ||X_a - X_b||^2
 struct DoubleSq {
   const double* p;
   __device__ double operator()(long e) const { return p[e]; }
+};
+struct DoubleDot {        // <a, b>
+  const double* a; const double* b;
+  __device__ double operator()(long e) const { return a[e] * b[e]; }
 };
 
 // ------------------------------------------------------------- element-wise
@@ -199,12 +221,22 @@ struct EpiStack {
   void* out[2];
   long ldo;
   int D, colblk;
+  // optional copy into a gradient operand of the differentiable form: row
+  // k colblk + col, K index koff + a (the same block seen with its two
+  // indices exchanged)
+  void* g[2] = {nullptr, nullptr};
+  long ldg = 0, koff = 0;
   __device__ __forceinline__ void operator()(int row, int col, typename ModeTraits<MODE>::Acc v) const {
     const int k = row / D;
     const int a = row - k * D;
     const long idx = op_index<MODE>(a, (long)k * colblk + col, ldo);
     if constexpr (MODE == M_F64) store_planes<MODE>(out, idx, v);
     else store_planes_f<MODE>(out, idx, v);
+    if (g[0]) {
+      const long gi = op_index<MODE>((long)k * colblk + col, koff + a, ldg);
+      if constexpr (MODE == M_F64) store_planes<MODE>(g, gi, v);
+      else store_planes_f<MODE>(g, gi, v);
+    }
   }
 };
 
@@ -219,12 +251,20 @@ struct EpiResid {
   int m;
   double* copy;        // m x n, nullable
   int n;
+  // optional copy of R into a gradient operand: row i, K index koff + j
+  void* g[2] = {nullptr, nullptr};
+  long ldg = 0, koff = 0;
   __device__ __forceinline__ void operator()(int j, int i, Acc v) const {
     const Acc r = bobs_t ? v - bobs_t[(long)j * m + i] : v;
     const long idx = op_index<MODE>(j, i, ldo);
     if constexpr (MODE == M_F64) store_planes<MODE>(out, idx, r);
     else store_planes_f<MODE>(out, idx, r);
     if (copy) copy[(long)i * n + j] = static_cast<double>(r);
+    if (g[0]) {
+      const long gi = op_index<MODE>(i, koff + j, ldg);
+      if constexpr (MODE == M_F64) store_planes<MODE>(g, gi, r);
+      else store_planes_f<MODE>(g, gi, r);
+    }
   }
 };
 
@@ -319,6 +359,127 @@ struct EpiUpdateSeq {
                              beta[k - 1], beta[k], nonneg);
   }
 };
+
+// ------------------------------------------------- differentiable form
+// Step 1 and Step 3 of Algorithm 2 with FP64 iterates (G2 epilogue):
+// X_k = c1 Y_k - c2 G, Y_{k+1} = X_k + beta (X_k - X_{k-1}), written as FP64
+// (ynext may alias yin: each element is read and written by one thread) and
+// as the F1 operand planes of Y_{k+1}.
+template <int MODE>
+struct EpiUpd64 {
+  void* y[2];
+  long ldy;
+  const double* yin;
+  const double* xprev;
+  double* xout;
+  double* ynext;
+  int n;
+  double c1, c2, beta;
+  __device__ __forceinline__ void operator()(int i, int j, typename ModeTraits<MODE>::Acc g) const {
+    const long e = (long)i * n + j;
+    const double xk = c1 * yin[e] - c2 * static_cast<double>(g);
+    const double yn = __builtin_fma(beta, xk - xprev[e], xk);   // same rounding as momentum_start_kernel
+    xout[e] = xk;
+    ynext[e] = yn;
+    store_planes<MODE>(y, op_index<MODE>(i, j, ldy), yn);
+  }
+};
+
+// Adjoint of Step 1 with respect to Y_k (G2 epilogue): Ybar = c1 Xbar + A_s^T Rbar.
+template <int MODE>
+struct EpiYbar {
+  double* ybar;
+  const double* xbar;
+  int n;
+  double c1;
+  __device__ __forceinline__ void operator()(int i, int j, typename ModeTraits<MODE>::Acc v) const {
+    const long e = (long)i * n + j;
+    ybar[e] = c1 * xbar[e] + static_cast<double>(v);
+  }
+};
+
+// Accumulation of a factor-gradient product:
+// out[row rs + (col / cblk) cbs + col % cblk] += v.
+template <int MODE>
+struct EpiAcc64 {
+  double* out;
+  long rs, cbs;
+  int cblk;
+  __device__ __forceinline__ void operator()(int row, int col, typename ModeTraits<MODE>::Acc v) const {
+    const int cb = col / cblk;
+    const long o = (long)row * rs + (long)cb * cbs + (col - cb * cblk);
+    out[o] += static_cast<double>(v);
+  }
+};
+
+// Y_{c+1} = X_c + beta (X_c - X_{c-1}) from two stored iterates, as FP64 and
+// as the F1 operand planes.
+template <int MODE>
+__global__ void momentum_start_kernel(const double* xprev, const double* xc, double beta, double* y, void* p0,
+                                      void* p1, long ldp, int m, int n) {
+  void* p[2] = {p0, p1};
+  const long total = (long)m * n;
+  for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < total; e += (long)gridDim.x * blockDim.x) {
+    const double v = __builtin_fma(beta, xc[e] - xprev[e], xc[e]);   // as in EpiUpd64
+    y[e] = v;
+    const long i = e / n, j = e - i * n;
+    store_planes<MODE>(p, op_index<MODE>(i, j, ldp), v);
+  }
+}
+
+// Adjoint of Step 3 and the start of the adjoint of Step 1 at iteration k:
+// Xbar_k = dX + a1 Ybar_{k+1} - a2 Ybar_{k+2} (dX nullable), Gbar = -c2 Xbar_k
+// as FP64 (Xbar) and as F1 operand planes, and Gbar^T into the gradient
+// operand gt (row j, K index koff + i).
+template <int MODE>
+__global__ void adjoint_step_kernel(const double* dx, const double* yb1, const double* yb2, double a1, double a2,
+                                    double c2, double* xbar, void* p0, void* p1, long ldp, void* g0, void* g1,
+                                    long ldg, long koff, int m, int n) {
+  void* p[2] = {p0, p1};
+  void* g[2] = {g0, g1};
+  const long total = (long)m * n;
+  for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < total; e += (long)gridDim.x * blockDim.x) {
+    double xb = a1 * yb1[e] - a2 * yb2[e];
+    if (dx) xb += dx[e];
+    xbar[e] = xb;
+    const double gb = -c2 * xb;
+    const long i = e / n, j = e - i * n;
+    store_planes<MODE>(p, op_index<MODE>(i, j, ldp), gb);
+    store_planes<MODE>(g, op_index<MODE>(j, koff + i, ldg), gb);
+  }
+}
+
+// Transposed copy of an m x n FP64 matrix into a gradient operand: element
+// (i, j) goes to row j, K index koff + i.
+template <int MODE>
+__global__ void pack_t_kernel(const double* src, void* g0, void* g1, long ldg, long koff, int m, int n) {
+  void* g[2] = {g0, g1};
+  const long total = (long)m * n;
+  for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < total; e += (long)gridDim.x * blockDim.x) {
+    const long i = e / n, j = e - i * n;
+    store_planes<MODE>(g, op_index<MODE>(j, koff + i, ldg), src[e]);
+  }
+}
+
+// Zeroes K indices [k0, k1) of rows [0, rows) of an operand.
+template <int MODE>
+__global__ void zero_k_kernel(void* g0, void* g1, long ldg, long rows, long k0, long k1) {
+  void* g[2] = {g0, g1};
+  const long w = k1 - k0;
+  const long total = rows * w;
+  for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < total; e += (long)gridDim.x * blockDim.x) {
+    const long r = e / w, k = k0 + (e - r * w);
+    store_planes<MODE>(g, op_index<MODE>(r, k, ldg), 0.0);
+  }
+}
+
+static __global__ void fill_zero_kernel(double* p, long count) {
+  for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < count; e += (long)gridDim.x * blockDim.x) p[e] = 0.0;
+}
+
+static __global__ void copy_kernel(const double* src, double* dst, long count) {
+  for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < count; e += (long)gridDim.x * blockDim.x) dst[e] = src[e];
+}
 
 // One-thread kernel advancing the device iteration counter.
 static __global__ void advance_counter_kernel(int* counter) {

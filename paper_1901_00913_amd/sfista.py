@@ -33,7 +33,8 @@ PRECISIONS = {"fp64": 0, "fp32": 1, "bf16": 2, "fp16": 3, "bf16x3": 4}
 EXPORTS = ("kron_approx", "sfista_setup", "sfista_step", "sfista_solve", "sfista_apply",
            "sfista_set_timing", "sfista_kernel_times", "sfista_get_L", "sfista_destroy",
            "sfista_last_error", "sfista_batch_setup", "sfista_batch_solve", "sfista_batch_tiles",
-           "sfista_batch_destroy")
+           "sfista_batch_destroy", "sfista_diff_setup", "sfista_diff_forward", "sfista_diff_backward",
+           "sfista_diff_get_L", "sfista_diff_destroy")
 
 BATCH_AUTOTUNE = 1
 BATCH_GRAPH = 2
@@ -94,11 +95,18 @@ def lib() -> ctypes.CDLL:
     L.sfista_batch_tiles.argtypes = [vp, ctypes.POINTER(i)]
     L.sfista_batch_destroy.argtypes = [vp]
     L.sfista_batch_destroy.restype = None
+    L.sfista_diff_setup.argtypes = [vp, i, i, vp, vp, i, d, d, i, i, i, vp, ctypes.POINTER(vp)]
+    L.sfista_diff_forward.argtypes = [vp, vp]
+    L.sfista_diff_backward.argtypes = [vp, vp, vp, vp, ctypes.POINTER(d)]
+    L.sfista_diff_get_L.argtypes = [vp, ctypes.POINTER(d)]
+    L.sfista_diff_destroy.argtypes = [vp]
+    L.sfista_diff_destroy.restype = None
     L.sfista_last_error.argtypes = []
     L.sfista_last_error.restype = ctypes.c_char_p
     for name in ("kron_approx", "sfista_setup", "sfista_step", "sfista_solve", "sfista_apply", "sfista_get_L",
                  "sfista_set_timing", "sfista_kernel_times", "sfista_batch_setup", "sfista_batch_solve",
-                 "sfista_batch_tiles"):
+                 "sfista_batch_tiles", "sfista_diff_setup", "sfista_diff_forward", "sfista_diff_backward",
+                 "sfista_diff_get_L"):
         getattr(L, name).restype = ctypes.c_int
     _lib = L
     return L
@@ -269,3 +277,120 @@ class Batch:
             self.close()
         except Exception:
             pass
+
+
+class Unrolled:
+    """Differentiable unrolled sFISTA for one image: ``forward()`` runs
+    ``iters`` iterations of Algorithm 2 from zero (``L`` fixed, checkpoints
+    every ``ckpt`` iterations) and returns X; ``backward(dX)`` returns
+    ``(dA, dB, dlam)``, the gradient of a loss whose derivative in X is dX.
+    ``precision`` is "fp32" or "fp64"."""
+
+    def __init__(self, Bobs, A, B, lam: float, L: Optional[float] = None, iters: int = 50, ckpt: int = 10,
+                 precision: str = "fp32", stream=None):
+        m, n = Bobs.shape
+        r = A.shape[0]
+        if A.shape != (r, n, n) or B.shape != (r, m, m):
+            raise ValueError("A must be (r, n, n) and B (r, m, m) for Bobs of shape (m, n)")
+        self._h = None
+        self.shape, self.r, self.device = (m, n), r, Bobs.device
+        h = ctypes.c_void_p()
+        _check(lib().sfista_diff_setup(_dev_f64(Bobs, "Bobs"), m, n, _dev_f64(A, "A"), _dev_f64(B, "B"), r,
+                                       float(lam), float(L) if L is not None else 0.0, PRECISIONS[precision],
+                                       int(iters), int(ckpt), _stream(stream), ctypes.byref(h)))
+        self._h = h
+
+    @property
+    def L(self) -> float:
+        v = ctypes.c_double()
+        _check(lib().sfista_diff_get_L(self._h, ctypes.byref(v)))
+        return v.value
+
+    def forward(self):
+        import torch
+        X = torch.empty(self.shape, dtype=torch.float64, device=self.device)
+        _check(lib().sfista_diff_forward(self._h, X.data_ptr()))
+        return X
+
+    def backward(self, dX):
+        import torch
+        m, n = self.shape
+        dA = torch.empty((self.r, n, n), dtype=torch.float64, device=self.device)
+        dB = torch.empty((self.r, m, m), dtype=torch.float64, device=self.device)
+        dlam = ctypes.c_double()
+        _check(lib().sfista_diff_backward(self._h, _dev_f64(dX.contiguous(), "dX"), dA.data_ptr(), dB.data_ptr(),
+                                          ctypes.byref(dlam)))
+        return dA, dB, dlam.value
+
+    def close(self):
+        if self._h is not None:
+            lib().sfista_diff_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def _unrolled_function():
+    import torch
+
+    class SfistaUnrolledFn(torch.autograd.Function):
+        """Batch of images, each restored by ``iters`` unrolled iterations;
+        gradients flow to the factors and lambda through the library's
+        adjoint (L and Bobs are constants)."""
+
+        @staticmethod
+        def forward(ctx, A, B, lam, Bobs, L, iters, ckpt, precision):
+            N = Bobs.shape[0]
+            if L is None:
+                Ls = [None] * N
+            else:
+                Lv = [float(v) for v in np.asarray(L.detach().cpu() if isinstance(L, torch.Tensor) else L,
+                                                   dtype=np.float64).reshape(-1)]
+                Ls = Lv * N if len(Lv) == 1 else Lv
+            lams = lam.detach().reshape(-1).expand(N).tolist()
+            plans, outs = [], []
+            streams = [torch.cuda.Stream(device=Bobs.device) for _ in range(N)]
+            cur = torch.cuda.current_stream(Bobs.device)
+            for k in range(N):
+                streams[k].wait_stream(cur)
+            for k in range(N):
+                with torch.cuda.stream(streams[k]):
+                    u = Unrolled(Bobs[k].detach().contiguous(), A[k].detach().contiguous(), B[k].detach().contiguous(),
+                                 lams[k], Ls[k], iters, ckpt, precision, stream=streams[k])
+                    outs.append(u.forward())
+                    plans.append(u)
+            for k in range(N):
+                cur.wait_stream(streams[k])
+            ctx.plans = plans
+            ctx.lam_shape = lam.shape
+            return torch.stack(outs)
+
+        @staticmethod
+        def backward(ctx, dX):
+            N = dX.shape[0]
+            dA, dB, dl = [], [], []
+            for k in range(N):
+                a, b, l = ctx.plans[k].backward(dX[k].to(torch.float64))
+                dA.append(a)
+                dB.append(b)
+                dl.append(l)
+            for u in ctx.plans:
+                u.close()
+            dlam = torch.tensor(dl, dtype=torch.float64, device=dX.device)
+            dlam = dlam.sum().reshape(ctx.lam_shape) if len(ctx.lam_shape) == 0 or ctx.lam_shape.numel() == 1 \
+                else dlam.reshape(ctx.lam_shape)
+            return torch.stack(dA), torch.stack(dB), dlam, None, None, None, None, None
+
+    return SfistaUnrolledFn
+
+
+def unrolled(A, B, lam, Bobs, L=None, iters: int = 50, ckpt: int = 10, precision: str = "fp32"):
+    """X = unrolled sFISTA of a batch: A (N, r, n, n), B (N, r, m, m), lam a
+    scalar or (N,) tensor, Bobs (N, m, n), all float64 on the GPU; L None
+    (power estimate per image), a float, or (N,) values.  Differentiable in
+    A, B and lam with torch.autograd."""
+    return _unrolled_function().apply(A, B, lam, Bobs, L, iters, ckpt, precision)

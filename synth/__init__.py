@@ -24,4 +24,5 @@ from .inputs import (  # noqa: F401
     motion_psf,
     power_start,
     batch_problems,
+    diff_problems,
 )

@@ -210,3 +210,14 @@ def batch_problems(count: int = 64, seed: int = SEED_BATCH + 4, sizes=None,
         out.append(_problem(f"batch-{t}", n, n, psf, bc, r, lam, iters, 0.01, 4,
                             "fp32", seed_shift=10 * t))
     return out
+
+
+def diff_problems(count: int = 8, n: int = 512, r: int = 4, iters: int = 50) -> List[Problem]:
+    """Differentiable-form batch: ``count`` images of size ``n``, each blurred
+    by one shared rotated Gaussian PSF (sigma = (3, 8), theta = 45 deg,
+    reflexive boundary), 1% noise, lambda = 0.01, rank ``r``; the images and
+    the noise differ per item (seeds of configuration 5 shifted by 10 per
+    item)."""
+    psf = gaussian_psf(n, n, (3.0, 8.0), 45.0)
+    return [_problem(f"diff-{t}", n, n, psf, BC_REFLEXIVE, r, 0.01, iters, 0.01, 5, "fp32", seed_shift=10 * t)
+            for t in range(count)]

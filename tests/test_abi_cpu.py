@@ -131,3 +131,30 @@ def test_batch_calls_reject_null(L):
     assert L.sfista_batch_solve(None, 1, None, None) == -1
     assert L.sfista_batch_tiles(None, (ctypes.c_int * 4)()) == -1
     L.sfista_batch_destroy(None)
+
+
+@pytest.mark.parametrize("args,expect", [
+    (dict(precision=4), -2),          # BF16X3 is not offered in the differentiable form
+    (dict(iters=0), -1),
+    (dict(ckpt=0), -1),
+    (dict(m=0), -1),
+    (dict(r=7, m=4, n=4), -1),
+    (dict(lam=-1.0), -1),
+])
+def test_diff_setup_rejects_invalid_arguments(L, args, expect):
+    a = dict(m=4, n=4, r=1, lam=0.1, Lc=1.0, precision=1, iters=5, ckpt=2)
+    a.update(args)
+    h = ctypes.c_void_p()
+    rc = L.sfista_diff_setup(FAKE, a["m"], a["n"], FAKE, FAKE, a["r"], a["lam"], a["Lc"], a["precision"],
+                             a["iters"], a["ckpt"], None, ctypes.byref(h))
+    assert rc == expect
+    assert h.value is None
+
+
+def test_diff_calls_reject_null(L):
+    d = ctypes.c_double()
+    assert L.sfista_diff_setup(FAKE, 4, 4, FAKE, FAKE, 1, 0.1, 1.0, 1, 5, 2, None, None) == -1
+    assert L.sfista_diff_forward(None, None) == -1
+    assert L.sfista_diff_backward(None, FAKE, FAKE, FAKE, ctypes.byref(d)) == -1
+    assert L.sfista_diff_get_L(None, ctypes.byref(d)) == -1
+    L.sfista_diff_destroy(None)
