@@ -33,12 +33,13 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def measured_traffic(gemm_index, precision, m, n, r):
-    """HBM bytes per launch of one GEMM from the committed rocprofv3 counter
-    summary, or None when it does not apply (other workload) or the GEMM
-    source changed since the counters were taken."""
+def measured_traffic(kernel, precision, m, n, r):
+    """HBM bytes per launch of a GEMM kernel from the committed rocprofv3
+    counter summary (FETCH_SIZE + WRITE_SIZE, each scaled by the counters'
+    reading of a plain copy), or None when it does not apply (other workload)
+    or the GEMM source changed since the counters were taken."""
     import hashlib
-    path = os.path.join(ROOT, "profiles", "gemm_nt_bf16x3_2048_r5_traffic.txt")
+    path = os.path.join(ROOT, "profiles", "gemm_planned_bf16x3_2048_r5_traffic.txt")
     if not (precision == "bf16x3" and m == n == 2048 and r == 5 and os.path.exists(path)):
         return None
     fields = {}
@@ -50,7 +51,8 @@ def measured_traffic(gemm_index, precision, m, n, r):
     src = os.path.join(ROOT, "paper_1901_00913_amd", "csrc", "gemm.hpp")
     if fields.get("gemm_source_sha256", [""])[0] != hashlib.sha256(open(src, "rb").read()).hexdigest():
         return None
-    row = fields.get("F1,G1" if gemm_index in (0, 2) else "F2,G2")
+    tag = kernel.split("<")[1].split(">")[0] if "<" in kernel else kernel
+    row = fields.get(tag)
     if not row:
         return None
     vals = dict(zip(row[0::2], row[1::2]))
@@ -128,6 +130,75 @@ def run_batch(args, dev, steps, warmup):
     return {"line": line, "summary": summary}
 
 
+DIFF_COUNT, DIFF_N, DIFF_R, DIFF_ITERS, DIFF_CKPT = 8, 512, 4, 50, 10
+
+
+def run_diff(args, dev, steps, warmup):
+    """Differentiable form: 8 images at 512^2 with one shared reflexive
+    Gaussian blur (r = 4 factors from the GPU Kronecker approximation), 50
+    unrolled FP32 iterations with checkpoints every 10, loss = mean squared
+    error to the true images; a step is the forward pass and the backward
+    pass to every factor entry and lambda (L estimated once, held fixed)."""
+    import numpy as np
+    import torch
+
+    import synth as S
+    from paper_1901_00913_amd import sfista
+
+    log(f"[diff] generating {DIFF_COUNT} problems at {DIFF_N}^2")
+    probs = S.diff_problems(count=DIFF_COUNT, n=DIFF_N, r=DIFF_R, iters=DIFF_ITERS)
+    p0 = probs[0]
+    l, q = p0.center
+    A1, B1, _, _ = sfista.kron_approx(torch.as_tensor(p0.psf).to(dev), l, q, p0.bc, DIFF_R)
+    L = sfista.Solver(torch.as_tensor(p0.bobs).to(dev), A1, B1, lam=p0.lam, precision="fp32", power_iters=30).L
+    A = A1.unsqueeze(0).repeat(DIFF_COUNT, 1, 1, 1).contiguous().requires_grad_(True)
+    B = B1.unsqueeze(0).repeat(DIFF_COUNT, 1, 1, 1).contiguous().requires_grad_(True)
+    lam = torch.tensor(p0.lam, dtype=torch.float64, device=dev, requires_grad=True)
+    Bobs = torch.tensor(np.stack([p.bobs for p in probs]), device=dev)
+    xt = torch.tensor(np.stack([p.x_true for p in probs]), device=dev)
+    n = DIFF_N
+    # per iteration: 12 products of 2 r n^3 (forward, recompute, adjoint: F1, F2, G1, G2 each) and the
+    # two factor-gradient products of 2 (r n) n (2 n) each
+    flops_img = DIFF_ITERS * (12 * 2.0 * DIFF_R * n ** 3 + 2 * 4.0 * DIFF_R * n ** 3)
+
+    def step():
+        A.grad = B.grad = lam.grad = None
+        X = sfista.unrolled(A, B, lam, Bobs, L=L, iters=DIFF_ITERS, ckpt=DIFF_CKPT, precision="fp32")
+        loss = ((X - xt) ** 2).mean(dim=(1, 2)).sum()
+        loss.backward()
+        return loss.detach().item()
+
+    for w in range(warmup):
+        log(f"[diff] warmup step {w + 1}/{warmup}")
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    losses = [step() for _ in range(steps)]
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    value = DIFF_COUNT * steps / elapsed
+    achieved = flops_img * DIFF_COUNT * steps / elapsed / 1e12
+    peak = PEAK_TFLOPS["fp32"]
+    log(f"[diff] {steps} steps in {elapsed:.3f} s -> {value:.2f} image-gradients/s, {achieved:.1f} TFLOP/s")
+    summary = {"image_gradients_per_s": value, "ms_per_step": elapsed / steps * 1e3, "alg_tflops": achieved,
+               "fp32_mfma_frac": achieved / peak, "loss": losses[-1], "L": L,
+               "dlam": float(lam.grad), "grad_norm_A": float(A.grad.norm()), "grad_norm_B": float(B.grad.norm())}
+    line = {
+        "metric": "sFISTA unrolled-gradient throughput, 8 images 512^2, r=4, 50 iterations",
+        "value": value, "unit": "image-gradients/s", "n_gpus": 1, "steps": steps, "warmup": warmup,
+        "ms_per_step": elapsed / steps * 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "fp32", "data": "synthetic",
+        "config": {"workload": f"sfista-diff{DIFF_COUNT}-{n}-r{DIFF_R}-{DIFF_ITERS}it-ckpt{DIFF_CKPT}",
+                   "images": DIFF_COUNT, "iters": DIFF_ITERS, "precision": "fp32", "parallelism": "single-gpu"},
+        "roofline": {"bound": "mfma", "kernel": "gemm_planned (forward, recompute, adjoint and gradient GEMMs)",
+                     "achieved": achieved, "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak,
+                     "traffic": None},
+        "cpu_baseline": None,
+        "extra": summary,
+    }
+    return {"line": line, "summary": summary}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -140,10 +211,12 @@ def main():
     ap.add_argument("--cpu-iters", type=int, default=3, help="oracle iterations timed for cpu_baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp32-compare", action="store_true")
-    ap.add_argument("--workload", default="precision-2048", choices=("precision-2048", "batch64"),
+    ap.add_argument("--workload", default="precision-2048", choices=("precision-2048", "batch64", "diff8"),
                     help="precision-2048: one 2048^2 image, r = 5 (default); batch64: 64 uneven images "
-                         "in grouped launches replayed from a HIP graph")
+                         "in grouped launches replayed from a HIP graph; diff8: gradient of 50 unrolled "
+                         "iterations for 8 images at 512^2, r = 4")
     ap.add_argument("--no-batch", action="store_true", help="skip the batch64 summary in the default line")
+    ap.add_argument("--no-diff", action="store_true", help="skip the diff8 summary in the default line")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="after the timed steps, copy a BYTES-long device buffer once (a plain copy kernel "
                          "of known traffic, for scaling hardware byte counters)")
@@ -166,8 +239,8 @@ def main():
     sfista.lib()
     dev = torch.device("cuda:0")
 
-    if args.workload == "batch64":
-        res = run_batch(args, dev, args.steps, args.warmup)
+    if args.workload in ("batch64", "diff8"):
+        res = (run_batch if args.workload == "batch64" else run_diff)(args, dev, args.steps, args.warmup)
         print(json.dumps(res["line"]), flush=True)
         return
 
@@ -208,17 +281,29 @@ def main():
     value = iters * args.steps / elapsed
     log(f"[bench] {args.steps} steps in {elapsed:.3f} s -> {value:.1f} it/s")
 
-    # per-GEMM mean device times over the timed steps
-    avg = [0.0] * 4
-    cnt = [0] * 4
+    # mean device times over the timed steps: GEMM kernels (0..3) and the
+    # reductions of their K-split tiles (4..7)
+    tot = [0.0] * 8
+    cnt = [0] * 8
     for ms, c in kts:
-        for g in range(4):
-            avg[g] += ms[g] * c[g]
+        for g in range(8):
+            tot[g] += ms[g] * c[g]
             cnt[g] += c[g]
-    avg = [a / c if c else 0.0 for a, c in zip(avg, cnt)]
+    avg = [t / c if c else 0.0 for t, c in zip(tot, cnt)]
     flops = [2.0 * r * m * n * n, 2.0 * r * m * m * n, 2.0 * r * m * m * n, 2.0 * r * m * n * n]
-    dom = max(range(4), key=lambda g: avg[g] * cnt[g])
-    achieved = flops[dom] / (avg[dom] * 1e-3) / 1e12
+    # kernels as rocprofv3 names them: F1 and G1 share one instantiation
+    groups = {"gemm_planned_kernel<EpiStack> (F1, G1)": [0, 2], "gemm_planned_kernel<EpiResid> (F2)": [1],
+              "gemm_planned_kernel<EpiUpdate> (G2)": [3]}
+    gstat = {}
+    for name, idx in groups.items():
+        t = sum(tot[i] for i in idx)
+        c = sum(cnt[i] for i in idx)
+        f = sum(flops[i] * cnt[i] for i in idx) / max(c, 1)
+        gstat[name] = {"total_ms": t, "launches": c, "avg_ms": t / max(c, 1), "alg_flops_per_launch": f}
+    dom = max(gstat, key=lambda k: gstat[k]["total_ms"])
+    mult = MFMA_PER_PRODUCT[args.precision]
+    achieved_alg = gstat[dom]["alg_flops_per_launch"] / (gstat[dom]["avg_ms"] * 1e-3) / 1e12
+    achieved = achieved_alg * mult   # executed MFMA flops (three bf16 products per product for bf16x3)
     peak = PEAK_TFLOPS[args.precision]
     iter_s = float(np.mean([rp["seconds"] for rp in reps]))
     iter_rate = iters / iter_s
@@ -228,8 +313,10 @@ def main():
         "iteration_only_its": iter_rate,
         "iteration_alg_tflops": alg_tflops_iter,
         "setup_ms_per_step": elapsed / args.steps * 1e3 - iter_s * 1e3,
-        "gemm_avg_ms": dict(zip(GEMM_NAMES, avg)),
+        "gemm_avg_ms": dict(zip(GEMM_NAMES, avg[:4])),
+        "split_reduce_avg_ms": dict(zip(GEMM_NAMES, avg[4:])),
         "gemm_alg_tflops": {GEMM_NAMES[g]: flops[g] / (avg[g] * 1e-3) / 1e12 for g in range(4) if avg[g] > 0},
+        "iteration_mfma_util": (alg_tflops_iter or 0.0) * mult / peak,
         "L": L, "eps_s": eps, "resid_rel": reps[-1]["resid_rel"], "phi_s": reps[-1]["phi_s"],
     }
 
@@ -278,6 +365,8 @@ def main():
 
     if not args.no_batch:
         extra["batch64"] = run_batch(args, dev, 1, 1)["summary"]
+    if not args.no_diff:
+        extra["diff8"] = run_diff(args, dev, 1, 1)["summary"]
 
     out = {
         "metric": METRIC, "value": value, "unit": "iters/s", "n_gpus": 1, "steps": args.steps,
@@ -286,11 +375,11 @@ def main():
         "config": {"workload": f"sfista-{m}x{n}-r{r}-reflexive-{iters}it", "image": [m, n], "rank": r,
                    "iters": iters, "precision": args.precision, "lambda": lam,
                    "power_iters": args.power_iters, "parallelism": "single-gpu"},
-        "roofline": {"bound": "mfma", "kernel": f"gemm_nt ({GEMM_NAMES[dom]})", "achieved": achieved,
-                     "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak,
-                     "traffic": measured_traffic(dom, args.precision, m, n, r),
-                     "mfma_products_per_flop": MFMA_PER_PRODUCT[args.precision],
-                     "mfma_util": achieved * MFMA_PER_PRODUCT[args.precision] / peak},
+        "roofline": {"bound": "mfma", "kernel": dom, "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
+                     "frac": achieved / peak, "traffic": measured_traffic(dom, args.precision, m, n, r),
+                     "flops_basis": "executed MFMA flops per launch (bf16x3: 3 bf16 products of 2*M*N*K)",
+                     "achieved_algorithmic": achieved_alg, "avg_launch_ms": gstat[dom]["avg_ms"],
+                     "launches": gstat[dom]["launches"]},
         "cpu_baseline": cpu,
         "extra": extra,
     }

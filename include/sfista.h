@@ -143,10 +143,11 @@ int sfista_apply(sfista_handle h, const double* X, double* AX, double* AtAX);
  * F2: R = sum_k B_k T_k - Bobs, G1: S_k = B_k^T R, G2: sum_k S_k A_k with the
  * fused update).  While enabled, every GEMM launch of sfista_step /
  * sfista_solve is bracketed by HIP events on the plan's stream.
- * sfista_kernel_times synchronises the stream and returns, per GEMM
- * (index 0..3 = F1, F2, G1, G2), the mean device time in milliseconds
- * (avg_ms, host, 4 entries) and the number of timed launches (launches, host,
- * 4 entries), then clears the accumulated samples. */
+ * sfista_kernel_times synchronises the stream and returns, per GEMM, the
+ * mean device time in milliseconds (avg_ms, host, 8 entries) and the number
+ * of timed launches (launches, host, 8 entries): index 0..3 = the GEMM kernel
+ * of F1, F2, G1, G2; index 4..7 = the reduction of their K-split tiles
+ * (0 when a product has none).  The samples are then cleared. */
 int sfista_set_timing(sfista_handle h, int enable);
 int sfista_kernel_times(sfista_handle h, double* avg_ms, long* launches);
 

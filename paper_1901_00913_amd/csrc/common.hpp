@@ -85,6 +85,41 @@ __device__ __forceinline__ void store_planes_f(void* const* p, long idx, float v
   }
 }
 
+// Eight consecutive K values of one operand row, starting at element idx of
+// a chunk-aligned K index (a multiple of 8): one 16-byte chunk per plane for
+// the 2-byte modes, two 16-byte chunks (16 rows apart) for FP32.  `vlo`
+// carries the low words of float-float values (BF16X3 only).
+template <int MODE>
+__device__ __forceinline__ void store8_planes(void* const* p, long idx, const float (&v)[8], const float (&vlo)[8]) {
+  if constexpr (MODE == M_F32) {
+    float* d = static_cast<float*>(p[0]) + idx;
+    *reinterpret_cast<float4*>(d) = make_float4(v[0], v[1], v[2], v[3]);
+    *reinterpret_cast<float4*>(d + 64) = make_float4(v[4], v[5], v[6], v[7]);   // next chunk: 16 rows x 4 values on
+  } else if constexpr (MODE == M_BF16 || MODE == M_F16 || MODE == M_BF16X3) {
+    uint32_t w0[4], w1[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      uint16_t h0, h1, l0 = 0, l1 = 0;
+      if constexpr (MODE == M_F16) {
+        h0 = f32_to_f16(v[2 * q]);
+        h1 = f32_to_f16(v[2 * q + 1]);
+      } else {
+        h0 = f32_to_bf16(v[2 * q]);
+        h1 = f32_to_bf16(v[2 * q + 1]);
+        if constexpr (MODE == M_BF16X3) {
+          l0 = f32_to_bf16((v[2 * q] - bf16_to_f32(h0)) + vlo[2 * q]);
+          l1 = f32_to_bf16((v[2 * q + 1] - bf16_to_f32(h1)) + vlo[2 * q + 1]);
+        }
+      }
+      w0[q] = static_cast<uint32_t>(h0) | (static_cast<uint32_t>(h1) << 16);
+      w1[q] = static_cast<uint32_t>(l0) | (static_cast<uint32_t>(l1) << 16);
+    }
+    *reinterpret_cast<uint4*>(static_cast<uint16_t*>(p[0]) + idx) = make_uint4(w0[0], w0[1], w0[2], w0[3]);
+    if constexpr (MODE == M_BF16X3)
+      *reinterpret_cast<uint4*>(static_cast<uint16_t*>(p[1]) + idx) = make_uint4(w1[0], w1[1], w1[2], w1[3]);
+  }
+}
+
 // ---------------------------------------------------------------- float-float
 // Error-free transformations (Knuth two-sum, Dekker/FMA two-product).  The
 // pragmas keep the compiler from contracting the exact sums.

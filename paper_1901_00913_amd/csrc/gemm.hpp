@@ -29,6 +29,7 @@
 #pragma once
 
 #include <algorithm>
+#include <type_traits>
 #include <vector>
 
 #include "common.hpp"
@@ -83,12 +84,50 @@ __device__ __forceinline__ void mma_chunk(typename AccVec<MODE>::T& acc, const u
   }
 }
 
+// Epilogues that also take eight consecutive columns of a row at once
+// (store8) get their outputs staged through LDS (see gemm_tile).
+template <class E, class = void>
+struct HasStore8 : std::false_type {};
+template <class E>
+struct HasStore8<E, std::void_t<decltype(&E::store8)>> : std::true_type {};
+// Epilogues whose per-element work is dominated by element-wise state
+// traffic opt out of the eight-column grouping in the split reduction
+// (there one element per thread keeps those accesses coalesced).
+template <class E, class = void>
+struct ReduceVec8 : std::true_type {};
+template <class E>
+struct ReduceVec8<E, std::void_t<decltype(E::kElementwiseReduce)>> : std::false_type {};
+
 // s_waitcnt immediate that waits until at most N vector-memory operations
 // are outstanding (expcnt and lgkmcnt left at their no-wait maxima).
 template <int N>
 constexpr int vmcnt_imm() {
   static_assert(N >= 0 && N < 64, "vmcnt range");
   return (N & 0xF) | (0x7 << 4) | (0xF << 8) | ((N >> 4) << 14);
+}
+
+// Staged epilogue of fragment row I and the rows after it (a compile-time
+// recursion, so every accumulator index is a constant even when the
+// epilogue body is too large for the compiler to unroll a loop over rows).
+template <int I, int FM, int FN, int GPR, int GPL, int SP, class AccT, class Epi>
+__device__ __forceinline__ void stage_rows(const AccT (&acc)[FM][FN], float* stg, int lane, int rbase, int cbase,
+                                           int M, int N, const Epi& epi) {
+  if constexpr (I < FM) {
+#pragma unroll
+    for (int j = 0; j < FN; ++j)
+#pragma unroll
+      for (int t = 0; t < 4; ++t) stg[((lane >> 4) * 4 + t) * SP + j * 16 + (lane & 15)] = acc[I][j][t];
+    for (int q = 0; q < GPL; ++q) {
+      const int gi = q * 64 + lane;
+      const int lr = gi / GPR, lc = (gi - lr * GPR) * 8;
+      const float4 u0 = *reinterpret_cast<const float4*>(stg + lr * SP + lc);
+      const float4 u1 = *reinterpret_cast<const float4*>(stg + lr * SP + lc + 4);
+      const float v[8] = {u0.x, u0.y, u0.z, u0.w, u1.x, u1.y, u1.z, u1.w};
+      const int row = rbase + I * 16 + lr, col = cbase + lc;
+      if (row < M && col < N) epi.store8(row, col, v, min(8, N - col));
+    }
+    stage_rows<I + 1, FM, FN, GPR, GPL, SP>(acc, stg, lane, rbase, cbase, M, N, epi);
+  }
 }
 
 // LDS staging: two buffers (two distinct __shared__ arrays, so the compiler
@@ -221,6 +260,27 @@ __device__ __forceinline__ void gemm_tile(unsigned char* lds0, unsigned char* ld
 #undef SF_LD
 #undef SF_TOP
 
+  // Staged epilogue: each wave writes one 16-row fragment row of its
+  // accumulators to a private LDS area (row-major), then every lane takes
+  // eight consecutive columns of a row, so the epilogue stores whole 16-byte
+  // chunks of the operand layout instead of single elements.  Both stage
+  // buffers are free once every wave's copies have landed and all waves have
+  // passed the barrier below.
+  if constexpr (std::is_same<typename Tr::Acc, float>::value && HasStore8<Epi>::value) {
+    __builtin_amdgcn_s_waitcnt(vmcnt_imm<0>());
+    __builtin_amdgcn_s_barrier();
+    asm volatile("" ::: "memory");
+    constexpr int SP = WN + 4;                  // padded staging row (floats)
+    constexpr int HALF = NW / 2;
+    constexpr int GPR = WN / 8;                 // groups of 8 per staged row
+    constexpr int GPL = 16 * GPR / 64;          // groups per lane per fragment row
+    static_assert(NW % 2 == 0 && (16 * GPR) % 64 == 0, "staging shape");
+    static_assert(HALF * 16 * SP * 4 <= T::template buf_bytes<MODE>(), "staging fits one stage buffer");
+    float* stg = reinterpret_cast<float*>((wave < HALF ? lds0 : lds1) + (wave % HALF) * (16 * SP * 4));
+    stage_rows<0, FM, FN, GPR, GPL, SP>(acc, stg, lane, tm * BM + wm * WM, tn * BN + wn * WN, g.M, g.N, epi);
+    return;
+  }
+
   // epilogue
   constexpr int RSTEP = (MODE == M_F64) ? 4 : 1;          // row stride between accumulator registers
   const int row0 = tm * BM + wm * WM + (lane >> 4) * (MODE == M_F64 ? 1 : 4);
@@ -317,6 +377,17 @@ struct EpiSlot {
   __device__ __forceinline__ void operator()(int row, int col, Acc v) const {
     ws[(long)(row - r0) * bn + (col - c0)] = v;
   }
+  __device__ __forceinline__ void store8(int row, int col, const float (&v)[8], int cnt) const {
+    if constexpr (std::is_same<Acc, float>::value) {
+      Acc* d = ws + (long)(row - r0) * bn + (col - c0);
+      if (cnt == 8) {
+        *reinterpret_cast<float4*>(d) = make_float4(v[0], v[1], v[2], v[3]);
+        *reinterpret_cast<float4*>(d + 4) = make_float4(v[4], v[5], v[6], v[7]);
+        return;
+      }
+      for (int q = 0; q < cnt; ++q) d[q] = v[q];
+    }
+  }
 };
 
 template <int MODE, class T, class Epi>
@@ -343,6 +414,27 @@ template <class Acc, class Epi, int BM, int BN>
 __global__ void tile_reduce_kernel(const Acc* ws, int S, int M, int N, const int2* tiles, Epi epi) {
   const int2 t = tiles[blockIdx.x];
   const Acc* base = ws + (long)blockIdx.x * S * (BM * BN);
+  if constexpr (std::is_same<Acc, float>::value && HasStore8<Epi>::value && ReduceVec8<Epi>::value) {
+    // eight consecutive columns per thread: vector loads of every split, one
+    // vector store through the epilogue
+    for (int q = blockIdx.y * blockDim.x + threadIdx.x; q < BM * BN / 8; q += gridDim.y * blockDim.x) {
+      const int lr = q / (BN / 8), lc = (q - lr * (BN / 8)) * 8;
+      const int row = t.x * BM + lr, col = t.y * BN + lc;
+      if (row >= M || col >= N) continue;
+      const float* p = base + lr * BN + lc;
+      float4 a = *reinterpret_cast<const float4*>(p);
+      float4 b = *reinterpret_cast<const float4*>(p + 4);
+      for (int z = 1; z < S; ++z) {
+        const float4 a2 = *reinterpret_cast<const float4*>(p + (long)z * (BM * BN));
+        const float4 b2 = *reinterpret_cast<const float4*>(p + (long)z * (BM * BN) + 4);
+        a.x += a2.x; a.y += a2.y; a.z += a2.z; a.w += a2.w;
+        b.x += b2.x; b.y += b2.y; b.z += b2.z; b.w += b2.w;
+      }
+      const float v[8] = {a.x, a.y, a.z, a.w, b.x, b.y, b.z, b.w};
+      epi.store8(row, col, v, min(8, N - col));
+    }
+    return;
+  }
   for (int e = blockIdx.y * blockDim.x + threadIdx.x; e < BM * BN; e += gridDim.y * blockDim.x) {
     const int lr = e / BN, lc = e - lr * BN;
     const int row = t.x * BM + lr, col = t.y * BN + lc;
@@ -428,15 +520,16 @@ struct GemmPlanDev {
 // reduction that applies `epi`.  `ws` holds nsplit x S x BM x BN values.
 template <int MODE, class Epi>
 hipError_t launch_planned(GemmArgs g, const Epi& epi, const GemmPlanDev& pl, typename ModeTraits<MODE>::Acc* ws,
-                          hipStream_t s) {
+                          hipStream_t s, hipEvent_t mid = nullptr) {
   using T = typename BigTile<MODE>::T;
   using Acc = typename ModeTraits<MODE>::Acc;
   if (g.M <= 0 || g.N <= 0 || pl.nitems == 0) return hipSuccess;
   g.kchunk = pl.kchunk;
   hipLaunchKernelGGL((gemm_planned_kernel<MODE, T, Epi>), dim3(pl.nitems), dim3(T::THREADS), 0, s, g, epi, ws,
                      pl.S, pl.items);
+  if (mid) (void)hipEventRecord(mid, s);
   if (pl.nsplit > 0)
-    hipLaunchKernelGGL((tile_reduce_kernel<Acc, Epi, T::BM, T::BN>), dim3(pl.nsplit, 16), dim3(256), 0, s, ws,
+    hipLaunchKernelGGL((tile_reduce_kernel<Acc, Epi, T::BM, T::BN>), dim3(pl.nsplit, 32), dim3(256), 0, s, ws,
                        pl.S, g.M, g.N, pl.split_tiles, epi);
   return hipGetLastError();
 }

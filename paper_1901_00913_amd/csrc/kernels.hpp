@@ -238,6 +238,21 @@ struct EpiStack {
       else store_planes_f<MODE>(g, gi, v);
     }
   }
+  // columns col .. col + cnt - 1 of one row (cnt <= 8): one vector store
+  // when they fill a chunk-aligned group
+  __device__ __forceinline__ void store8(int row, int col, const float (&v)[8], int cnt) const {
+    if constexpr (MODE != M_F64) {
+      const int k = row / D;
+      const int a = row - k * D;
+      const long k0 = (long)k * colblk + col;
+      if (cnt == 8 && (k0 & 7) == 0 && !g[0]) {
+        const float z[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+        store8_planes<MODE>(out, op_index<MODE>(a, k0, ldo), v, z);
+        return;
+      }
+    }
+    for (int q = 0; q < cnt; ++q) (*this)(row, col + q, v[q]);
+  }
 };
 
 // F2: R^T[j][i] = (sum_k B_k T_k)^T[j][i] - Bobs^T[j][i] (Step 1's inner
@@ -266,6 +281,19 @@ struct EpiResid {
       else store_planes_f<MODE>(g, gi, r);
     }
   }
+  __device__ __forceinline__ void store8(int j, int i, const float (&v)[8], int cnt) const {
+    if constexpr (MODE != M_F64) {
+      if (cnt == 8 && (i & 7) == 0 && !copy && !g[0]) {
+        float r[8];
+        const float z[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int q = 0; q < 8; ++q) r[q] = bobs_t ? v[q] - bobs_t[(long)j * m + i + q] : v[q];
+        store8_planes<MODE>(out, op_index<MODE>(j, i, ldo), r, z);
+        return;
+      }
+    }
+    for (int q = 0; q < cnt; ++q) (*this)(j, i + q, v[q]);
+  }
 };
 
 // G2 without update: raw FP64 copy of the normal-operator product.
@@ -284,6 +312,37 @@ struct EpiStore {
 //   Y_{k+1} = X_k + beta_k (X_k - X_{k-1})
 // X_k overwrites X_{k-2} in place (state index s); the planes of Y_{k+1}
 // (operand index o) feed the next iteration's F1.
+// State update of one element for the float-state kinds (Steps 1 and 3 of
+// Algorithm 2 with the Tikhonov scaling and the optional x >= 0 projection):
+// reads X_{k-1} (x1) and X_{k-2} (x2), writes X_k over X_{k-2} and returns
+// Y_{k+1} as a (hi, lo) float pair (lo = 0 for plain FP32 state).
+template <int KIND>
+__device__ __forceinline__ void update_state(const void* x1, void* x2, long s, float g, double c1, double c2,
+                                             double bp, double bc, int nonneg, float& yh, float& yl) {
+  if constexpr (KIND == ST_PAIR) {
+    const float2 p1 = static_cast<const float2*>(x1)[s];
+    const float2 p2 = static_cast<float2*>(x2)[s];
+    const ff a1{p1.x, p1.y}, a2{p2.x, p2.y};
+    const ff yk = ff_add(a1, ff_mul(ff_from_double(bp), ff_add(a1, ff_neg(a2))));
+    ff xk = ff_add(ff_mul(ff_from_double(c1), yk), ff_neg(ff_mul_f(ff_from_double(c2), g)));
+    if (nonneg && (xk.hi < 0.f || (xk.hi == 0.f && xk.lo < 0.f))) xk = ff{0.f, 0.f};
+    const ff yn = ff_add(xk, ff_mul(ff_from_double(bc), ff_add(xk, ff_neg(a1))));
+    static_cast<float2*>(x2)[s] = make_float2(xk.hi, xk.lo);
+    yh = yn.hi;
+    yl = yn.lo;
+  } else {
+    const float a1 = static_cast<const float*>(x1)[s];
+    const float a2 = static_cast<float*>(x2)[s];
+    const float yk = a1 + static_cast<float>(bp) * (a1 - a2);
+    float xk = static_cast<float>(c1) * yk - static_cast<float>(c2) * g;
+    if (nonneg) xk = fmaxf(xk, 0.f);
+    const float yn = xk + static_cast<float>(bc) * (xk - a1);
+    static_cast<float*>(x2)[s] = xk;
+    yh = yn;
+    yl = 0.f;
+  }
+}
+
 template <int MODE, int KIND>
 __device__ __forceinline__ void update_point(void* const* y, long o, const void* x1, void* x2, long s,
                                              typename ModeTraits<MODE>::Acc g, double c1, double c2, double bp,
@@ -297,26 +356,31 @@ __device__ __forceinline__ void update_point(void* const* y, long o, const void*
     const double yn = xk + bc * (xk - a1);
     static_cast<double*>(x2)[s] = xk;
     store_planes<MODE>(y, o, yn);
-  } else if constexpr (KIND == ST_PAIR) {
-    const float2 p1 = static_cast<const float2*>(x1)[s];
-    const float2 p2 = static_cast<float2*>(x2)[s];
-    const ff a1{p1.x, p1.y}, a2{p2.x, p2.y};
-    const ff yk = ff_add(a1, ff_mul(ff_from_double(bp), ff_add(a1, ff_neg(a2))));
-    ff xk = ff_add(ff_mul(ff_from_double(c1), yk), ff_neg(ff_mul_f(ff_from_double(c2), static_cast<float>(g))));
-    if (nonneg && (xk.hi < 0.f || (xk.hi == 0.f && xk.lo < 0.f))) xk = ff{0.f, 0.f};
-    const ff yn = ff_add(xk, ff_mul(ff_from_double(bc), ff_add(xk, ff_neg(a1))));
-    static_cast<float2*>(x2)[s] = make_float2(xk.hi, xk.lo);
-    store_planes_f<MODE>(y, o, yn.hi, yn.lo);
   } else {
-    const float a1 = static_cast<const float*>(x1)[s];
-    const float a2 = static_cast<float*>(x2)[s];
-    const float yk = a1 + static_cast<float>(bp) * (a1 - a2);
-    float xk = static_cast<float>(c1) * yk - static_cast<float>(c2) * static_cast<float>(g);
-    if (nonneg) xk = fmaxf(xk, 0.f);
-    const float yn = xk + static_cast<float>(bc) * (xk - a1);
-    static_cast<float*>(x2)[s] = xk;
-    store_planes_f<MODE>(y, o, yn);
+    float yh, yl;
+    update_state<KIND>(x1, x2, s, static_cast<float>(g), c1, c2, bp, bc, nonneg, yh, yl);
+    store_planes_f<MODE>(y, o, yh, yl);
   }
+}
+
+// Eight consecutive columns (j chunk-aligned) of the update with one vector
+// store of Y_{k+1}; anything else falls back to single elements.
+template <int MODE, int KIND, class E>
+__device__ __forceinline__ void update_store8(const E& e, int i, int j, const float (&g)[8], int cnt, const void* x1,
+                                              void* x2, double bp, double bc) {
+  if constexpr (KIND != ST_F64 && MODE != M_F64) {
+    if (cnt == 8 && (j & 7) == 0) {
+      float yh[8], yl[8];
+      const long s0 = (long)i * e.n + j;
+#pragma unroll
+      for (int q = 0; q < 8; ++q) update_state<KIND>(x1, x2, s0 + q, g[q], e.c1, e.c2, bp, bc, e.nonneg, yh[q], yl[q]);
+      store8_planes<MODE>(e.y, op_index<MODE>(i, j, e.ldy), yh, yl);
+      return;
+    }
+  }
+  for (int q = 0; q < cnt; ++q)
+    update_point<MODE, KIND>(e.y, op_index<MODE>(i, j + q, e.ldy), x1, x2, (long)i * e.n + j + q, g[q], e.c1, e.c2,
+                             bp, bc, e.nonneg);
 }
 
 // G2 epilogue with the iteration's constants passed by the host.
@@ -335,6 +399,10 @@ struct EpiUpdate {
     update_point<MODE, KIND>(y, op_index<MODE>(i, j, ldy), x1, const_cast<void*>(x2), (long)i * n + j, g, c1, c2,
                              bp, bc, nonneg);
   }
+  __device__ __forceinline__ void store8(int i, int j, const float (&g)[8], int cnt) const {
+    update_store8<MODE, KIND>(*this, i, j, g, cnt, x1, x2, bp, bc);
+  }
+  static constexpr bool kElementwiseReduce = true;
 };
 
 // G2 epilogue that reads the iteration number k = *counter + 1 and the
@@ -358,6 +426,13 @@ struct EpiUpdateSeq {
     update_point<MODE, KIND>(y, op_index<MODE>(i, j, ldy), x1, x2, (long)i * n + j, g, c1, c2,
                              beta[k - 1], beta[k], nonneg);
   }
+  __device__ __forceinline__ void store8(int i, int j, const float (&g)[8], int cnt) const {
+    const int k = *counter + 1;
+    void* const x1 = (k & 1) ? st[0] : st[1];
+    void* const x2 = (k & 1) ? st[1] : st[0];
+    update_store8<MODE, KIND>(*this, i, j, g, cnt, x1, x2, beta[k - 1], beta[k]);
+  }
+  static constexpr bool kElementwiseReduce = true;
 };
 
 // ------------------------------------------------- differentiable form

@@ -38,8 +38,9 @@ struct sfista_plan {
   std::vector<hipEvent_t> ev_pool;
   size_t ev_used = 0;
   std::vector<std::pair<int, size_t>> ev_marks;   // (gemm kind, index of the start event)
-  double t_sum[4] = {0, 0, 0, 0};
-  long t_cnt[4] = {0, 0, 0, 0};
+  hipEvent_t mid_ev = nullptr;                     // recorded between a GEMM and its split reduction
+  double t_sum[8] = {0, 0, 0, 0, 0, 0, 0, 0};      // GEMM kernels 0..3, their reductions 4..7
+  long t_cnt[8] = {0, 0, 0, 0, 0, 0, 0, 0};
   DeviceArena arena;
   ~sfista_plan() {
     for (hipEvent_t e : ev_pool) (void)hipEventDestroy(e);
@@ -69,15 +70,19 @@ hipEvent_t next_event(sfista_plan* h) {
   return h->ev_pool[h->ev_used++];
 }
 
-// Brackets one GEMM launch with events when timing is enabled.
+// Brackets one GEMM launch with events when timing is enabled: start, after
+// the GEMM kernel (mid_ev, recorded by launch_planned) and after its split
+// reduction.
 template <class F>
 hipError_t timed(sfista_plan* h, int kind, F&& launch) {
   if (!h->timing) return launch();
   const size_t idx = h->ev_used;
-  hipEvent_t a = next_event(h), b = next_event(h);
-  if (!a || !b) return hipErrorOutOfMemory;
+  hipEvent_t a = next_event(h), mid = next_event(h), b = next_event(h);
+  if (!a || !mid || !b) return hipErrorOutOfMemory;
   (void)hipEventRecord(a, h->s);
+  h->mid_ev = mid;
   hipError_t e = launch();
+  h->mid_ev = nullptr;
   (void)hipEventRecord(b, h->s);
   h->ev_marks.push_back({kind, idx});
   return e;
@@ -88,10 +93,13 @@ hipError_t collect_times(sfista_plan* h) {
   hipError_t e = hipStreamSynchronize(h->s);
   if (e != hipSuccess) return e;
   for (auto& mk : h->ev_marks) {
-    float ms = 0.f;
-    if ((e = hipEventElapsedTime(&ms, h->ev_pool[mk.second], h->ev_pool[mk.second + 1])) != hipSuccess) return e;
-    h->t_sum[mk.first] += ms;
+    float g = 0.f, r = 0.f;
+    if ((e = hipEventElapsedTime(&g, h->ev_pool[mk.second], h->ev_pool[mk.second + 1])) != hipSuccess) return e;
+    if ((e = hipEventElapsedTime(&r, h->ev_pool[mk.second + 1], h->ev_pool[mk.second + 2])) != hipSuccess) return e;
+    h->t_sum[mk.first] += g;
     h->t_cnt[mk.first] += 1;
+    h->t_sum[4 + mk.first] += r;
+    h->t_cnt[4 + mk.first] += 1;
   }
   h->ev_marks.clear();
   h->ev_used = 0;
@@ -132,7 +140,7 @@ hipError_t run_f1(sfista_plan* h, void* const* y, long ldy) {
   EpiStack<MODE> e;
   e.out[0] = h->T[0]; e.out[1] = h->T[1]; e.ldo = h->ldT; e.D = h->n; e.colblk = h->m;
   return launch_planned<MODE>(gargs<MODE>(h->W, h->ldW, y, ldy, h->r * h->n, h->m, h->n), e, h->pl[0], ws_of<MODE>(h),
-                              h->s);
+                              h->s, h->mid_ev);
 }
 
 // F2: R^T = (sum_k B_k T_k)^T - Bobs^T   (bobs optional)
@@ -143,7 +151,7 @@ hipError_t run_f2(sfista_plan* h, bool with_bobs, double* copy) {
   e.bobs_t = with_bobs ? static_cast<const typename ModeTraits<MODE>::Acc*>(h->bobs_t) : nullptr;
   e.m = h->m; e.copy = copy; e.n = h->n;
   return launch_planned<MODE>(gargs<MODE>(h->T, h->ldT, h->Bc, h->ldBc, h->n, h->m, h->r * h->m), e, h->pl[1],
-                              ws_of<MODE>(h), h->s);
+                              ws_of<MODE>(h), h->s, h->mid_ev);
 }
 
 // G1: S_k = B_k^T R for all k, stored side by side (m x rn): S[i][k n + j].
@@ -152,14 +160,14 @@ hipError_t run_g1(sfista_plan* h) {
   EpiStack<MODE> e;
   e.out[0] = h->S[0]; e.out[1] = h->S[1]; e.ldo = h->ldS; e.D = h->m; e.colblk = h->n;
   return launch_planned<MODE>(gargs<MODE>(h->Bt, h->ldBt, h->R, h->ldR, h->r * h->m, h->n, h->m), e, h->pl[2],
-                              ws_of<MODE>(h), h->s);
+                              ws_of<MODE>(h), h->s, h->mid_ev);
 }
 
 // G2 with an arbitrary epilogue: sum_k S_k A_k.
 template <int MODE, class Epi>
 hipError_t run_g2(sfista_plan* h, const Epi& e) {
   return launch_planned<MODE>(gargs<MODE>(h->S, h->ldS, h->At, h->ldAt, h->m, h->n, h->r * h->n), e, h->pl[3],
-                              ws_of<MODE>(h), h->s);
+                              ws_of<MODE>(h), h->s, h->mid_ev);
 }
 
 template <int MODE>
@@ -535,7 +543,7 @@ int sfista_kernel_times(sfista_handle h, double* avg_ms, long* launches) {
   if (!h || !avg_ms || !launches) return set_error(SFISTA_ERR_ARG, "NULL argument");
   hipError_t e = collect_times(h);
   if (e != hipSuccess) return hip_fail(e, "sfista_kernel_times");
-  for (int k = 0; k < 4; ++k) {
+  for (int k = 0; k < 8; ++k) {
     avg_ms[k] = h->t_cnt[k] ? h->t_sum[k] / h->t_cnt[k] : 0.0;
     launches[k] = h->t_cnt[k];
     h->t_sum[k] = 0.0;

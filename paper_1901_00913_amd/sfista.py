@@ -200,10 +200,11 @@ class Solver:
         _check(lib().sfista_set_timing(self._h, int(bool(enable))))
 
     def kernel_times(self):
-        """Mean device milliseconds and launch counts of the four GEMMs
-        (F1, F2, G1, G2) timed since the last call."""
-        ms = (ctypes.c_double * 4)()
-        cnt = (ctypes.c_long * 4)()
+        """Mean device milliseconds and launch counts since the last call:
+        entries 0..3 the GEMM kernels of F1, F2, G1, G2, entries 4..7 the
+        reductions of their K-split tiles."""
+        ms = (ctypes.c_double * 8)()
+        cnt = (ctypes.c_long * 8)()
         _check(lib().sfista_kernel_times(self._h, ms, cnt))
         return list(ms), list(cnt)
 
@@ -334,6 +335,15 @@ class Unrolled:
             pass
 
 
+def _map_threads(fn, count):
+    """fn(0..count-1) on host threads (the library calls release the GIL), in order."""
+    if count == 1:
+        return [fn(0)]
+    from concurrent.futures import ThreadPoolExecutor
+    with ThreadPoolExecutor(max_workers=min(count, 16)) as ex:
+        return list(ex.map(fn, range(count)))
+
+
 def _unrolled_function():
     import torch
 
@@ -352,32 +362,48 @@ def _unrolled_function():
                                                    dtype=np.float64).reshape(-1)]
                 Ls = Lv * N if len(Lv) == 1 else Lv
             lams = lam.detach().reshape(-1).expand(N).tolist()
-            plans, outs = [], []
             streams = [torch.cuda.Stream(device=Bobs.device) for _ in range(N)]
             cur = torch.cuda.current_stream(Bobs.device)
             for k in range(N):
                 streams[k].wait_stream(cur)
-            for k in range(N):
+            Ad, Bd, Od = A.detach(), B.detach(), Bobs.detach()
+
+            def one(k):   # each image on its own stream, driven from its own host thread
                 with torch.cuda.stream(streams[k]):
-                    u = Unrolled(Bobs[k].detach().contiguous(), A[k].detach().contiguous(), B[k].detach().contiguous(),
-                                 lams[k], Ls[k], iters, ckpt, precision, stream=streams[k])
-                    outs.append(u.forward())
-                    plans.append(u)
+                    u = Unrolled(Od[k].contiguous(), Ad[k].contiguous(), Bd[k].contiguous(), lams[k], Ls[k], iters,
+                                 ckpt, precision, stream=streams[k])
+                    return u, u.forward()
+
+            res = _map_threads(one, N)
             for k in range(N):
                 cur.wait_stream(streams[k])
-            ctx.plans = plans
+                res[k][1].record_stream(cur)   # made on stream k, consumed on the caller's stream
+            ctx.plans = [u for u, _ in res]
+            ctx.streams = streams
             ctx.lam_shape = lam.shape
-            return torch.stack(outs)
+            return torch.stack([x for _, x in res])
 
         @staticmethod
         def backward(ctx, dX):
             N = dX.shape[0]
-            dA, dB, dl = [], [], []
-            for k in range(N):
-                a, b, l = ctx.plans[k].backward(dX[k].to(torch.float64))
-                dA.append(a)
-                dB.append(b)
-                dl.append(l)
+            dXd = dX.to(torch.float64).contiguous()
+            cur = torch.cuda.current_stream(dX.device)
+            for st in ctx.streams:
+                st.wait_stream(cur)
+
+            def one(k):
+                with torch.cuda.stream(ctx.streams[k]):
+                    return ctx.plans[k].backward(dXd[k])
+
+            res = _map_threads(one, N)
+            for st in ctx.streams:
+                cur.wait_stream(st)
+            for a, b, _ in res:
+                a.record_stream(cur)
+                b.record_stream(cur)
+            dA = [a for a, _, _ in res]
+            dB = [b for _, b, _ in res]
+            dl = [l for _, _, l in res]
             for u in ctx.plans:
                 u.close()
             dlam = torch.tensor(dl, dtype=torch.float64, device=dX.device)
