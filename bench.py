@@ -199,6 +199,64 @@ def run_diff(args, dev, steps, warmup):
     return {"line": line, "summary": summary}
 
 
+def run_paper(args, dev, steps, warmup):
+    """The paper's experiment shape (Section 4) on synthetic stand-ins: 256^2
+    images, reflexive boundary, 1% noise, a defocus and a motion PSF, s = 1..5
+    Kronecker terms, 50 iterations in FP64 (as the paper's double precision),
+    lambda = 0.02.  Per (PSF, s): eps_s = ||A - A_s||_F (Theorem 1), the
+    restoration error eta = ||X - x_true|| / ||x_true|| and the approximate
+    residual gamma_s, and the time of the setup and of the iterations.  A step
+    is the whole sweep; `value` is sweeps per second."""
+    import numpy as np
+    import torch
+
+    import synth as S
+    from paper_1901_00913_amd import sfista
+
+    probs = S.paper_problems(256, iters=50)
+    dat = {k: (torch.as_tensor(p.psf).to(dev), torch.as_tensor(p.bobs).to(dev), p) for k, p in probs.items()}
+
+    def sweep():
+        rows = []
+        for kind, (P, Bo, p) in dat.items():
+            l, q = p.center
+            for s_ in range(1, 6):
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                A, B, sig, eps = sfista.kron_approx(P, l, q, p.bc, s_)
+                sol = sfista.Solver(Bo, A, B, lam=p.lam, precision="fp64", power_iters=50)
+                torch.cuda.synchronize()
+                t1 = time.perf_counter()
+                X, rep = sol.solve(p.iters)
+                sol.close()
+                eta = float(np.linalg.norm(X.cpu().numpy() - p.x_true) / np.linalg.norm(p.x_true))
+                rows.append({"psf": kind, "s": s_, "eps_s": eps, "eta": eta, "gamma_s": rep["resid_rel"],
+                             "setup_ms": (t1 - t0) * 1e3, "iter_ms": rep["seconds"] * 1e3})
+        return rows
+
+    for w in range(warmup):
+        log(f"[paper] warmup sweep {w + 1}/{warmup}")
+        sweep()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    out = [sweep() for _ in range(steps)]
+    elapsed = time.perf_counter() - t0
+    rows = out[-1]
+    for r_ in rows:
+        log(f"[paper] {r_['psf']:8s} s={r_['s']} eps_s={r_['eps_s']:.4e} eta={r_['eta']:.4f} "
+            f"gamma_s={r_['gamma_s']:.4e} setup {r_['setup_ms']:.1f} ms, 50 its {r_['iter_ms']:.2f} ms")
+    line = {
+        "metric": "paper-shaped sweep (256^2, s=1..5, defocus and motion, 50 iterations FP64)",
+        "value": steps / elapsed, "unit": "sweeps/s", "n_gpus": 1, "steps": steps, "warmup": warmup,
+        "ms_per_step": elapsed / steps * 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "fp64", "data": "synthetic",
+        "config": {"workload": "sfista-paper-256-s1..5-50it", "image": [256, 256], "iters": 50,
+                   "precision": "fp64", "parallelism": "single-gpu"},
+        "roofline": None, "cpu_baseline": None, "extra": {"rows": rows},
+    }
+    return {"line": line, "summary": rows}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -211,10 +269,12 @@ def main():
     ap.add_argument("--cpu-iters", type=int, default=3, help="oracle iterations timed for cpu_baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp32-compare", action="store_true")
-    ap.add_argument("--workload", default="precision-2048", choices=("precision-2048", "batch64", "diff8"),
+    ap.add_argument("--workload", default="precision-2048",
+                    choices=("precision-2048", "batch64", "diff8", "paper256"),
                     help="precision-2048: one 2048^2 image, r = 5 (default); batch64: 64 uneven images "
                          "in grouped launches replayed from a HIP graph; diff8: gradient of 50 unrolled "
-                         "iterations for 8 images at 512^2, r = 4")
+                         "iterations for 8 images at 512^2, r = 4; paper256: the paper-shaped sweep "
+                         "(256^2, reflexive, 1% noise, defocus and motion blur, s = 1..5, 50 iterations)")
     ap.add_argument("--no-batch", action="store_true", help="skip the batch64 summary in the default line")
     ap.add_argument("--no-diff", action="store_true", help="skip the diff8 summary in the default line")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
@@ -239,8 +299,9 @@ def main():
     sfista.lib()
     dev = torch.device("cuda:0")
 
-    if args.workload in ("batch64", "diff8"):
-        res = (run_batch if args.workload == "batch64" else run_diff)(args, dev, args.steps, args.warmup)
+    if args.workload in ("batch64", "diff8", "paper256"):
+        res = {"batch64": run_batch, "diff8": run_diff, "paper256": run_paper}[args.workload](
+            args, dev, args.steps, args.warmup)
         print(json.dumps(res["line"]), flush=True)
         return
 

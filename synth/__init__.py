@@ -25,4 +25,6 @@ from .inputs import (  # noqa: F401
     power_start,
     batch_problems,
     diff_problems,
+    defocus_psf,
+    paper_problems,
 )

@@ -103,6 +103,18 @@ def motion_psf(m: int, n: int, length: float = 15.0, angle_deg: float = 30.0,
     return p / p.sum()
 
 
+def defocus_psf(m: int, n: int, radius: float = 4.0, center: Optional[tuple] = None) -> np.ndarray:
+    """Out-of-focus blur: a uniform disk of ``radius`` pixels around the
+    centre, each pixel weighted by the covered fraction (4 x 4 subsamples),
+    normalised to sum 1."""
+    l, q = center if center is not None else (m // 2, n // 2)
+    sub = (np.arange(4) + 0.5) / 4.0 - 0.5
+    dy = (np.arange(m) - l)[:, None, None, None] + sub[None, None, :, None]
+    dx = (np.arange(n) - q)[None, :, None, None] + sub[None, None, None, :]
+    p = ((dy * dy + dx * dx) <= radius * radius).mean(axis=(2, 3))
+    return p / p.sum()
+
+
 def blur(x: np.ndarray, psf: np.ndarray, center: tuple, bc: int) -> np.ndarray:
     """Exact spatially invariant blur of ``x`` (the data model ``b = A x``).
 
@@ -221,3 +233,16 @@ def diff_problems(count: int = 8, n: int = 512, r: int = 4, iters: int = 50) -> 
     psf = gaussian_psf(n, n, (3.0, 8.0), 45.0)
     return [_problem(f"diff-{t}", n, n, psf, BC_REFLEXIVE, r, 0.01, iters, 0.01, 5, "fp32", seed_shift=10 * t)
             for t in range(count)]
+
+
+def paper_problems(n: int = 256, iters: int = 50, lam: float = 0.02):
+    """Stand-ins for the paper's experiments (Section 4): an n x n image blurred
+    with a defocus disk (radius n/64) and, separately, with a motion blur
+    (length n/16 at 30 deg), reflexive boundary, 1% noise.  Returns a dict
+    kind -> Problem with r left at 5 (the sweep sets its own rank)."""
+    out = {}
+    for t, (kind, psf) in enumerate((("defocus", defocus_psf(n, n, n / 64.0)),
+                                     ("motion", motion_psf(n, n, n / 16.0, 30.0)))):
+        out[kind] = _problem(f"paper-{kind}", n, n, psf, BC_REFLEXIVE, 5, lam, iters, 0.01, 6, "fp64",
+                             seed_shift=10 * t)
+    return out
