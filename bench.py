@@ -190,7 +190,7 @@ def run_diff(args, dev, steps, warmup):
         "dtype": "fp32", "data": "synthetic",
         "config": {"workload": f"sfista-diff{DIFF_COUNT}-{n}-r{DIFF_R}-{DIFF_ITERS}it-ckpt{DIFF_CKPT}",
                    "images": DIFF_COUNT, "iters": DIFF_ITERS, "precision": "fp32", "parallelism": "single-gpu"},
-        "roofline": {"bound": "mfma", "kernel": "gemm_planned (forward, recompute, adjoint and gradient GEMMs)",
+        "roofline": {"bound": "mfma", "kernel": "gemm_grouped (forward, recompute, adjoint and gradient GEMMs)",
                      "achieved": achieved, "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak,
                      "traffic": None},
         "cpu_baseline": None,

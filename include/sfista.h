@@ -218,23 +218,28 @@ void sfista_batch_destroy(sfista_batch_handle h);
  * iterates and adjoints are FP64 in both.  Buffers are device memory,
  * row-major, caller-owned; setup copies what it needs (inputs may be freed
  * afterwards).  L <= 0 asks for the power estimate (30 steps).  nonneg is
- * not supported in this form.
+ * not supported in this form.  The handle runs on the caller's stream and
+ * the calls return after their work has finished.
  * --------------------------------------------------------------------- */
 typedef struct sfista_diff* sfista_diff_handle;
 
-int sfista_diff_setup(const double* Bobs, int m, int n, const double* A, const double* B, int r, double lambda,
-                      double L, int precision, int iters, int ckpt_every, hipStream_t stream,
-                      sfista_diff_handle* out);
+/* One handle holds `count` problems (sfista_batch_item: Bobs, sizes, dense
+ * factors, lambda, L), all of the same rank r.  Each product of an
+ * iteration is one grouped launch over the tiles of all problems. */
+int sfista_diff_setup(const sfista_batch_item* items, int count, int precision, int iters, int ckpt_every,
+                      hipStream_t stream, sfista_diff_handle* out);
 
-/* Forward pass: X_out (m x n, FP64, nullable) receives X_iters.  May be
- * called again (it restarts from X_0). */
-int sfista_diff_forward(sfista_diff_handle h, double* X_out);
+/* Forward pass: X_out[b] (m x n, FP64, entries nullable, or X_out NULL)
+ * receives X_iters of problem b.  May be called again (it restarts from 0). */
+int sfista_diff_forward(sfista_diff_handle h, double* const* X_out);
 
-/* Backward pass after a forward pass: dX (m x n) in; dA (r x n x n) and dB
- * (r x m x m) are overwritten with the gradients; *dlambda (host) too. */
-int sfista_diff_backward(sfista_diff_handle h, const double* dX, double* dA, double* dB, double* dlambda);
+/* Backward pass after a forward pass: dX[b] (m x n) in; dA[b] (r x n x n) and
+ * dB[b] (r x m x m) are overwritten with the gradients; dlambda (host,
+ * `count` entries) too. */
+int sfista_diff_backward(sfista_diff_handle h, const double* const* dX, double* const* dA, double* const* dB,
+                         double* dlambda);
 
-/* The L in use (given or estimated). */
+/* The L in use per problem (host, `count` entries; given or estimated). */
 int sfista_diff_get_L(sfista_diff_handle h, double* L);
 
 void sfista_diff_destroy(sfista_diff_handle h);

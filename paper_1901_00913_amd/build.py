@@ -17,7 +17,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libsfista.so")
-SOURCES = ["sfista.hip", "kron.hip"]
+SOURCES = ["sfista.hip", "kron.hip", "diff.hip"]
 ARCH = os.environ.get("SFISTA_ARCH", "gfx950")
 
 HIPCC_FLAGS = [

@@ -11,54 +11,14 @@
 #include "../../include/sfista.h"
 #include "gemm.hpp"
 #include "kernels.hpp"
+#include "plan.hpp"
 #include "util.hpp"
 
 using namespace sf;
 
-struct sfista_plan {
-  int m = 0, n = 0, r = 0, mode = 0, nonneg = 0, kind = 0;
-  double lam = 0.0, L = 0.0;
-  hipStream_t s = nullptr;
-  long iter = 0;          // iterations completed (k)
-  double tk = 1.0;        // t_{k+1}: momentum parameter of the next iteration
-  double beta_prev = 0.0; // beta_k = (t_k - 1) / t_{k+1} of the last iteration
-  // leading dimensions (elements) of the packed operands
-  long ldW = 0, ldBc = 0, ldBt = 0, ldAt = 0, ldY = 0, ldT = 0, ldR = 0, ldS = 0;
-  void *W[2] = {}, *Bc[2] = {}, *Bt[2] = {}, *At[2] = {};
-  void *Y[2] = {}, *T[2] = {}, *R[2] = {}, *S[2] = {}, *Xop[2] = {};
-  void* bobs_t = nullptr;
-  void* st[2] = {};
-  double* aux = nullptr;      // m x n FP64 scratch (power iterate, copies)
-  double* red = nullptr;      // reduction partials [RED_BLOCKS] + scalars
-  void* ws = nullptr;         // K-split partials of the planned products
-  GemmPlanDev pl[4];          // work lists of F1, F2, G1, G2
-  double bobs_norm = 0.0;
-  // optional per-GEMM event timing
-  int timing = 0;
-  std::vector<hipEvent_t> ev_pool;
-  size_t ev_used = 0;
-  std::vector<std::pair<int, size_t>> ev_marks;   // (gemm kind, index of the start event)
-  hipEvent_t mid_ev = nullptr;                     // recorded between a GEMM and its split reduction
-  double t_sum[8] = {0, 0, 0, 0, 0, 0, 0, 0};      // GEMM kernels 0..3, their reductions 4..7
-  long t_cnt[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-  DeviceArena arena;
-  ~sfista_plan() {
-    for (hipEvent_t e : ev_pool) (void)hipEventDestroy(e);
-  }
-};
 
 namespace {
 
-constexpr int EW_BLOCKS = 2048;
-constexpr int EW_THREADS = 256;
-
-long ld_of(long k) { return round_up(k, TileCfg::K_PAD); }
-long rows_of(long r) { return round_up(r, TileCfg::ROW_PAD); }
-
-int state_kind(int mode, int pair) {
-  if (mode == M_F64) return ST_F64;
-  return pair ? ST_PAIR : ST_F32;
-}
 
 // ------------------------------------------------------------------ timing
 hipEvent_t next_event(sfista_plan* h) {
@@ -107,33 +67,6 @@ hipError_t collect_times(sfista_plan* h) {
 }
 
 // ------------------------------------------------------------------ GEMMs
-template <int MODE>
-GemmArgs gargs(void* const* a, long lda, void* const* b, long ldb, int M, int N, int K) {
-  GemmArgs g;
-  g.a[0] = a[0]; g.a[1] = a[1];
-  g.b[0] = b[0]; g.b[1] = b[1];
-  g.lda = lda; g.ldb = ldb;
-  g.M = M; g.N = N; g.K = K;
-  g.kchunk = 0;
-  return g;
-}
-
-template <int MODE>
-typename ModeTraits<MODE>::Acc* ws_of(sfista_plan* h) {
-  return static_cast<typename ModeTraits<MODE>::Acc*>(h->ws);
-}
-
-// Workgroups of the planned GEMM kernel resident per CU.
-template <int MODE>
-int resident_per_cu() {
-  using T = typename BigTile<MODE>::T;
-  int nb = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, gemm_planned_kernel<MODE, T, EpiStack<MODE>>, T::THREADS, 0) !=
-          hipSuccess || nb < 1)
-    nb = 1;
-  return nb;
-}
-
 // F1: T_k = Y A_k^T for all k, stored as T^T (n x rm):  Tt[j][k m + i].
 template <int MODE>
 hipError_t run_f1(sfista_plan* h, void* const* y, long ldy) {
@@ -406,25 +339,6 @@ hipError_t apply_mode(sfista_plan* h, const double* X, double* AX, double* AtAX)
 }  // namespace
 
 // ====================================================================== C ABI
-namespace {
-
-// Host-side checks of one problem, before any device work.
-int validate_problem(const double* Bobs, int m, int n, const double* A, const double* B, int r,
-                     const sfista_params* p) {
-  if (!Bobs || !A || !B || !p) return set_error(SFISTA_ERR_ARG, "NULL input pointer");
-  if (m < 1 || n < 1) return set_error(SFISTA_ERR_ARG, "image size %d x %d must be positive", m, n);
-  if (r < 1 || r > (m < n ? m : n)) return set_error(SFISTA_ERR_ARG, "rank r=%d must lie in [1, min(m,n)]", r);
-  if ((long)r * m > (1L << 30) || (long)r * n > (1L << 30))
-    return set_error(SFISTA_ERR_UNSUPPORTED, "r*m or r*n exceeds 2^30");
-  if (!isfinite(p->lambda) || p->lambda < 0.0) return set_error(SFISTA_ERR_ARG, "lambda must be finite and >= 0");
-  if (!isfinite(p->L)) return set_error(SFISTA_ERR_ARG, "L must be finite");
-  if (p->precision < SFISTA_FP64 || p->precision > SFISTA_BF16X3)
-    return set_error(SFISTA_ERR_UNSUPPORTED, "unknown precision %d", p->precision);
-  if (p->power_iters < 0) return set_error(SFISTA_ERR_ARG, "power_iters must be >= 0");
-  return SFISTA_OK;
-}
-
-}  // namespace
 
 extern "C" {
 
@@ -963,381 +877,5 @@ int sfista_batch_tiles(sfista_batch_handle b, int* choice) {
 }
 
 void sfista_batch_destroy(sfista_batch_handle b) { delete b; }
-
-}  // extern "C"
-
-// ======================================================================
-// Differentiable form
-// ======================================================================
-struct sfista_diff {
-  sfista_plan* p = nullptr;
-  int iters = 0, ckpt = 0, nseg = 0;
-  double lam = 0.0, L = 0.0, c1 = 0.0, c2 = 0.0;
-  std::vector<double> beta;          // beta[k] = (t_k - 1) / t_{k+1}, k = 0..iters+1 (beta[0] = 0)
-  double* ck = nullptr;              // checkpoint s: (X_{sC-1}, X_{sC}), 2 m n each
-  double* xs = nullptr;              // segment iterates, slot t = X_{c0-1+t}, t = 0..C+1
-  double* ys = nullptr;              // segment Y_k, slot t = Y_{c0+1+t}, t = 0..C
-  double* xbar = nullptr;
-  double* yb[3] = {};                // Ybar_{k+1}, Ybar_{k+2}, Ybar_k (rotated)
-  double* dots = nullptr;            // <Xbar_k, X_k>, k = 1..iters
-  void *BA[2] = {}, *GB[2] = {}, *AA[2] = {}, *AB[2] = {};
-  long ldBA = 0, ldGB = 0, ldAA = 0, ldAB = 0;
-  GemmPlanDev gpB, gpA;              // the two factor-gradient products
-  void* ws = nullptr;
-  bool forward_done = false;
-  DeviceArena arena;
-  ~sfista_diff() {
-    if (p) {
-      (void)hipStreamSynchronize(p->s);
-      delete p;
-    }
-  }
-};
-
-namespace {
-
-constexpr int DIFF_BLOCKS = 1024;
-
-template <int MODE>
-hipError_t upload_plan(sfista_diff* d, const GemmPlan& gp, GemmPlanDev& pd) {
-  hipStream_t s = d->p->s;
-  PlanItem* items = static_cast<PlanItem*>(d->arena.alloc_zero(gp.items.size() * sizeof(PlanItem), s));
-  int2* tiles = gp.split_tiles.empty() ? nullptr
-                                       : static_cast<int2*>(d->arena.alloc_zero(gp.split_tiles.size() * sizeof(int2), s));
-  if (!items || (!gp.split_tiles.empty() && !tiles)) return hipErrorOutOfMemory;
-  hipError_t e = hipMemcpyAsync(items, gp.items.data(), gp.items.size() * sizeof(PlanItem), hipMemcpyHostToDevice, s);
-  if (e == hipSuccess && tiles)
-    e = hipMemcpyAsync(tiles, gp.split_tiles.data(), gp.split_tiles.size() * sizeof(int2), hipMemcpyHostToDevice, s);
-  pd.items = items;
-  pd.split_tiles = tiles;
-  pd.nitems = (int)gp.items.size();
-  pd.nsplit = (int)gp.split_tiles.size();
-  pd.S = gp.S;
-  pd.kchunk = gp.kchunk;
-  return e;
-}
-
-template <int MODE>
-int diff_setup_mode(sfista_diff* d) {
-  using TB = typename BigTile<MODE>::T;
-  using Acc = typename ModeTraits<MODE>::Acc;
-  constexpr int P = ModeTraits<MODE>::planes;
-  constexpr int es = ModeTraits<MODE>::esize;
-  sfista_plan* h = d->p;
-  const int m = h->m, n = h->n, r = h->r, C = d->ckpt;
-  const long mn = (long)m * n;
-  hipStream_t s = h->s;
-  auto dbl = [&](size_t count) { return static_cast<double*>(d->arena.alloc_zero(count * sizeof(double), s)); };
-  d->ck = dbl((size_t)d->nseg * 2 * mn);
-  d->xs = dbl((size_t)(C + 2) * mn);
-  d->ys = dbl((size_t)(C + 1) * mn);
-  d->xbar = dbl(mn);
-  for (int q = 0; q < 3; ++q) d->yb[q] = dbl(mn);
-  d->dots = dbl((size_t)d->iters + 1);
-  if (!d->ck || !d->xs || !d->ys || !d->xbar || !d->yb[0] || !d->yb[1] || !d->yb[2] || !d->dots)
-    return set_error(SFISTA_ERR_NOMEM, "device allocation failed (%s)", d->arena.last_error());
-  d->ldBA = ld_of(2L * C * n);
-  d->ldGB = ld_of(2L * C * n);
-  d->ldAA = ld_of(2L * C * m);
-  d->ldAB = ld_of(2L * C * m);
-  auto planes = [&](void** dst, long rows, long ld) -> bool {
-    for (int q = 0; q < P; ++q) {
-      dst[q] = d->arena.alloc_zero((size_t)rows_of(rows) * ld * es, s);
-      if (!dst[q]) return false;
-    }
-    return true;
-  };
-  if (!planes(d->BA, m, d->ldBA) || !planes(d->GB, (long)r * m, d->ldGB) || !planes(d->AA, (long)r * n, d->ldAA) ||
-      !planes(d->AB, n, d->ldAB))
-    return set_error(SFISTA_ERR_NOMEM, "device allocation failed (%s)", d->arena.last_error());
-  int dev = 0, cus = 256;
-  hipDeviceProp_t prop;
-  if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess) cus = prop.multiProcessorCount;
-  const int slots = cus * resident_per_cu<MODE>();
-  const GemmPlan pB = plan_gemm<TB>(m, r * m, gemm_kstages<MODE>(2 * C * n), slots);
-  const GemmPlan pA = plan_gemm<TB>(r * n, n, gemm_kstages<MODE>(2 * C * m), slots);
-  hipError_t e;
-  if ((e = upload_plan<MODE>(d, pB, d->gpB)) != hipSuccess || (e = upload_plan<MODE>(d, pA, d->gpA)) != hipSuccess)
-    return hip_fail(e, "gradient plans");
-  const size_t ws = std::max(pB.ws_elems(), pA.ws_elems()) * TB::BM * TB::BN;
-  if (ws > 0 && !(d->ws = d->arena.alloc_zero(ws * sizeof(Acc), s)))
-    return set_error(SFISTA_ERR_NOMEM, "device allocation failed (%s)", d->arena.last_error());
-  if ((e = hipStreamSynchronize(s)) != hipSuccess) return hip_fail(e, "diff setup");
-  return SFISTA_OK;
-}
-
-// One iteration k of Algorithm 2 from Y_k (FP64 yin and the Y planes) and
-// X_{k-1}: writes X_k and Y_{k+1} (FP64 and planes).  With gslot >= 0 the
-// F1, F2 and G1 epilogues also place T_k, R_k and S_k, and Y_k^T is packed,
-// into the factor-gradient operands at iteration slot gslot.
-template <int MODE>
-hipError_t diff_iteration(sfista_diff* d, long k, const double* yin, const double* xprev, double* xout,
-                          double* ynext, int gslot) {
-  sfista_plan* h = d->p;
-  const int m = h->m, n = h->n, r = h->r;
-  hipError_t e;
-  {
-    EpiStack<MODE> ep;
-    ep.out[0] = h->T[0]; ep.out[1] = h->T[1]; ep.ldo = h->ldT; ep.D = n; ep.colblk = m;
-    if (gslot >= 0) { ep.g[0] = d->GB[0]; ep.g[1] = d->GB[1]; ep.ldg = d->ldGB; ep.koff = (2L * gslot + 1) * n; }
-    if ((e = launch_planned<MODE>(gargs<MODE>(h->W, h->ldW, h->Y, h->ldY, r * n, m, n), ep, h->pl[0], ws_of<MODE>(h),
-                                  h->s)) != hipSuccess)
-      return e;
-  }
-  {
-    EpiResid<MODE> ep;
-    ep.out[0] = h->R[0]; ep.out[1] = h->R[1]; ep.ldo = h->ldR;
-    ep.bobs_t = static_cast<const typename ModeTraits<MODE>::Acc*>(h->bobs_t); ep.m = m; ep.copy = nullptr; ep.n = n;
-    if (gslot >= 0) { ep.g[0] = d->BA[0]; ep.g[1] = d->BA[1]; ep.ldg = d->ldBA; ep.koff = 2L * gslot * n; }
-    if ((e = launch_planned<MODE>(gargs<MODE>(h->T, h->ldT, h->Bc, h->ldBc, n, m, r * m), ep, h->pl[1],
-                                  ws_of<MODE>(h), h->s)) != hipSuccess)
-      return e;
-  }
-  {
-    EpiStack<MODE> ep;
-    ep.out[0] = h->S[0]; ep.out[1] = h->S[1]; ep.ldo = h->ldS; ep.D = m; ep.colblk = n;
-    if (gslot >= 0) { ep.g[0] = d->AA[0]; ep.g[1] = d->AA[1]; ep.ldg = d->ldAA; ep.koff = 2L * gslot * m; }
-    if ((e = launch_planned<MODE>(gargs<MODE>(h->Bt, h->ldBt, h->R, h->ldR, r * m, n, m), ep, h->pl[2],
-                                  ws_of<MODE>(h), h->s)) != hipSuccess)
-      return e;
-  }
-  if (gslot >= 0)
-    hipLaunchKernelGGL(pack_t_kernel<MODE>, dim3(DIFF_BLOCKS), dim3(256), 0, h->s, yin, d->AB[0], d->AB[1], d->ldAB,
-                       (2L * gslot + 1) * m, m, n);
-  EpiUpd64<MODE> up;
-  up.y[0] = h->Y[0]; up.y[1] = h->Y[1]; up.ldy = h->ldY;
-  up.yin = yin; up.xprev = xprev; up.xout = xout; up.ynext = ynext; up.n = n;
-  up.c1 = d->c1; up.c2 = d->c2; up.beta = d->beta[k];
-  return launch_planned<MODE>(gargs<MODE>(h->S, h->ldS, h->At, h->ldAt, m, n, r * n), up, h->pl[3], ws_of<MODE>(h),
-                              h->s);
-}
-
-template <int MODE>
-hipError_t diff_forward_mode(sfista_diff* d, double* X_out) {
-  sfista_plan* h = d->p;
-  const int m = h->m, n = h->n;
-  const long mn = (long)m * n;
-  hipStream_t s = h->s;
-  // X_{-1} = X_0 = 0 in xs slots 0 and 1, Y_1 = X_0 in ys slot 0 and the Y planes
-  hipLaunchKernelGGL(fill_zero_kernel, dim3(DIFF_BLOCKS), dim3(256), 0, s, d->xs, 2 * mn);
-  hipLaunchKernelGGL(momentum_start_kernel<MODE>, dim3(DIFF_BLOCKS), dim3(256), 0, s, d->xs, d->xs + mn, 0.0, d->ys,
-                     h->Y[0], h->Y[1], h->ldY, m, n);
-  hipLaunchKernelGGL(fill_zero_kernel, dim3(DIFF_BLOCKS), dim3(256), 0, s, d->ck, 2 * mn);   // checkpoint 0
-  // X_k alternates between xs slots (k + 1) & 1 ... written as slot 2 + (k & 1) to keep X_{k-1}
-  double* xb[2] = {d->xs, d->xs + mn};   // xb[k & 1] = X_k (k >= 0), X_{-1} unused after k = 1
-  hipError_t e;
-  for (long k = 1; k <= d->iters; ++k) {
-    double* xprev = xb[(k - 1) & 1];
-    double* xout = xb[k & 1];
-    if ((e = diff_iteration<MODE>(d, k, d->ys, xprev, xout, d->ys, -1)) != hipSuccess) return e;
-    if (k % d->ckpt == 0 && k < d->iters) {
-      double* slot = d->ck + (k / d->ckpt) * 2 * mn;
-      hipLaunchKernelGGL(copy_kernel, dim3(DIFF_BLOCKS), dim3(256), 0, s, xprev, slot, mn);
-      hipLaunchKernelGGL(copy_kernel, dim3(DIFF_BLOCKS), dim3(256), 0, s, xout, slot + mn, mn);
-    }
-  }
-  if (X_out)
-    hipLaunchKernelGGL(copy_kernel, dim3(DIFF_BLOCKS), dim3(256), 0, s, xb[d->iters & 1], X_out, mn);
-  if ((e = hipGetLastError()) != hipSuccess) return e;
-  return hipStreamSynchronize(s);
-}
-
-template <int MODE>
-hipError_t diff_backward_mode(sfista_diff* d, const double* dX, double* dA, double* dB, double* dlam) {
-  sfista_plan* h = d->p;
-  const int m = h->m, n = h->n, r = h->r, C = d->ckpt;
-  const long mn = (long)m * n;
-  hipStream_t s = h->s;
-  hipError_t e;
-  hipLaunchKernelGGL(fill_zero_kernel, dim3(DIFF_BLOCKS), dim3(256), 0, s, dA, (long)r * n * n);
-  hipLaunchKernelGGL(fill_zero_kernel, dim3(DIFF_BLOCKS), dim3(256), 0, s, dB, (long)r * m * m);
-  hipLaunchKernelGGL(fill_zero_kernel, dim3(DIFF_BLOCKS), dim3(256), 0, s, d->yb[0], mn);
-  hipLaunchKernelGGL(fill_zero_kernel, dim3(DIFF_BLOCKS), dim3(256), 0, s, d->yb[1], mn);
-  double* yb1 = d->yb[0];   // Ybar_{k+1}
-  double* yb2 = d->yb[1];   // Ybar_{k+2}
-  double* ybn = d->yb[2];   // Ybar_k (being computed)
-  for (int sg = d->nseg - 1; sg >= 0; --sg) {
-    const long c0 = (long)sg * C;
-    const long c1 = std::min<long>(c0 + C, d->iters);
-    const int len = (int)(c1 - c0);
-    // recompute the segment from its checkpoint, filling the forward halves
-    // of the gradient operands
-    const double* ckp = d->ck + (long)sg * 2 * mn;
-    hipLaunchKernelGGL(copy_kernel, dim3(DIFF_BLOCKS), dim3(256), 0, s, ckp, d->xs, 2 * mn);
-    hipLaunchKernelGGL(momentum_start_kernel<MODE>, dim3(DIFF_BLOCKS), dim3(256), 0, s, d->xs, d->xs + mn,
-                       d->beta[c0], d->ys, h->Y[0], h->Y[1], h->ldY, m, n);
-    if (len < C) {   // unused iteration slots must hold zeros
-      hipLaunchKernelGGL(zero_k_kernel<MODE>, dim3(DIFF_BLOCKS), dim3(256), 0, s, d->BA[0], d->BA[1], d->ldBA, (long)m,
-                         2L * len * n, 2L * C * n);
-      hipLaunchKernelGGL(zero_k_kernel<MODE>, dim3(DIFF_BLOCKS), dim3(256), 0, s, d->GB[0], d->GB[1], d->ldGB,
-                         (long)r * m, 2L * len * n, 2L * C * n);
-      hipLaunchKernelGGL(zero_k_kernel<MODE>, dim3(DIFF_BLOCKS), dim3(256), 0, s, d->AA[0], d->AA[1], d->ldAA,
-                         (long)r * n, 2L * len * m, 2L * C * m);
-      hipLaunchKernelGGL(zero_k_kernel<MODE>, dim3(DIFF_BLOCKS), dim3(256), 0, s, d->AB[0], d->AB[1], d->ldAB, (long)n,
-                         2L * len * m, 2L * C * m);
-    }
-    for (long k = c0 + 1; k <= c1; ++k) {
-      const long t = k - c0;
-      if ((e = diff_iteration<MODE>(d, k, d->ys + (t - 1) * mn, d->xs + t * mn, d->xs + (t + 1) * mn, d->ys + t * mn,
-                                    (int)(t - 1))) != hipSuccess)
-        return e;
-    }
-    // adjoint sweep over the segment
-    for (long k = c1; k > c0; --k) {
-      const long t = k - c0;
-      const int gslot = (int)(t - 1);
-      const double a1 = 1.0 + d->beta[k];
-      const double a2 = d->beta[k + 1];
-      hipLaunchKernelGGL(adjoint_step_kernel<MODE>, dim3(DIFF_BLOCKS), dim3(256), 0, s, k == d->iters ? dX : nullptr,
-                         yb1, yb2, a1, a2, d->c2, d->xbar, h->Xop[0], h->Xop[1], h->ldY, d->AB[0], d->AB[1], d->ldAB,
-                         2L * gslot * m, m, n);
-      if ((e = sumf(DoubleDot{d->xbar, d->xs + (t + 1) * mn}, mn, h->red, d->dots + (k - 1), s)) != hipSuccess) return e;
-      {
-        EpiStack<MODE> ep;   // U = Gbar A^T
-        ep.out[0] = h->T[0]; ep.out[1] = h->T[1]; ep.ldo = h->ldT; ep.D = n; ep.colblk = m;
-        ep.g[0] = d->GB[0]; ep.g[1] = d->GB[1]; ep.ldg = d->ldGB; ep.koff = 2L * gslot * n;
-        if ((e = launch_planned<MODE>(gargs<MODE>(h->W, h->ldW, h->Xop, h->ldY, r * n, m, n), ep, h->pl[0],
-                                      ws_of<MODE>(h), s)) != hipSuccess)
-          return e;
-      }
-      {
-        EpiResid<MODE> ep;   // Rbar = A_s(Gbar)
-        ep.out[0] = h->R[0]; ep.out[1] = h->R[1]; ep.ldo = h->ldR; ep.bobs_t = nullptr; ep.m = m; ep.copy = nullptr;
-        ep.n = n;
-        ep.g[0] = d->BA[0]; ep.g[1] = d->BA[1]; ep.ldg = d->ldBA; ep.koff = (2L * gslot + 1) * n;
-        if ((e = launch_planned<MODE>(gargs<MODE>(h->T, h->ldT, h->Bc, h->ldBc, n, m, r * m), ep, h->pl[1],
-                                      ws_of<MODE>(h), s)) != hipSuccess)
-          return e;
-      }
-      {
-        EpiStack<MODE> ep;   // W = B^T Rbar
-        ep.out[0] = h->S[0]; ep.out[1] = h->S[1]; ep.ldo = h->ldS; ep.D = m; ep.colblk = n;
-        ep.g[0] = d->AA[0]; ep.g[1] = d->AA[1]; ep.ldg = d->ldAA; ep.koff = (2L * gslot + 1) * m;
-        if ((e = launch_planned<MODE>(gargs<MODE>(h->Bt, h->ldBt, h->R, h->ldR, r * m, n, m), ep, h->pl[2],
-                                      ws_of<MODE>(h), s)) != hipSuccess)
-          return e;
-      }
-      {
-        EpiYbar<MODE> ep;    // Ybar_k = c1 Xbar_k + A_s^T Rbar
-        ep.ybar = ybn; ep.xbar = d->xbar; ep.n = n; ep.c1 = d->c1;
-        if ((e = launch_planned<MODE>(gargs<MODE>(h->S, h->ldS, h->At, h->ldAt, m, n, r * n), ep, h->pl[3],
-                                      ws_of<MODE>(h), s)) != hipSuccess)
-          return e;
-      }
-      double* tmp = yb2;
-      yb2 = yb1;
-      yb1 = ybn;
-      ybn = tmp;
-    }
-    // factor gradients of the segment
-    {
-      EpiAcc64<MODE> ep;   // dB[j][x][y] += sum over the segment
-      ep.out = dB; ep.rs = m; ep.cbs = (long)m * m; ep.cblk = m;
-      GemmArgs g = gargs<MODE>(d->BA, d->ldBA, d->GB, d->ldGB, m, r * m, 2 * C * n);
-      if ((e = launch_planned<MODE>(g, ep, d->gpB, static_cast<typename ModeTraits<MODE>::Acc*>(d->ws), s)) !=
-          hipSuccess)
-        return e;
-    }
-    {
-      EpiAcc64<MODE> ep;   // dA[j][a][b] += sum over the segment
-      ep.out = dA; ep.rs = n; ep.cbs = n; ep.cblk = n;
-      GemmArgs g = gargs<MODE>(d->AA, d->ldAA, d->AB, d->ldAB, r * n, n, 2 * C * m);
-      if ((e = launch_planned<MODE>(g, ep, d->gpA, static_cast<typename ModeTraits<MODE>::Acc*>(d->ws), s)) !=
-          hipSuccess)
-        return e;
-    }
-  }
-  std::vector<double> dots(d->iters);
-  if ((e = hipMemcpyAsync(dots.data(), d->dots, sizeof(double) * d->iters, hipMemcpyDeviceToHost, s)) != hipSuccess)
-    return e;
-  if ((e = hipStreamSynchronize(s)) != hipSuccess) return e;
-  double acc = 0.0;
-  for (int k = 0; k < d->iters; ++k) acc += dots[k];
-  *dlam = acc * (-2.0 * d->lam / (d->L + d->lam * d->lam));
-  return hipSuccess;
-}
-
-}  // namespace
-
-extern "C" {
-
-int sfista_diff_setup(const double* Bobs, int m, int n, const double* A, const double* B, int r, double lambda,
-                      double L, int precision, int iters, int ckpt_every, hipStream_t stream,
-                      sfista_diff_handle* out) {
-  clear_error();
-  if (!out) return set_error(SFISTA_ERR_ARG, "out handle pointer is NULL");
-  *out = nullptr;
-  if (precision != SFISTA_FP32 && precision != SFISTA_FP64)
-    return set_error(SFISTA_ERR_UNSUPPORTED, "the differentiable form runs in FP32 or FP64 (got %d)", precision);
-  if (iters < 1 || ckpt_every < 1) return set_error(SFISTA_ERR_ARG, "iters and ckpt_every must be >= 1");
-  if (ckpt_every > iters) ckpt_every = iters;
-  sfista_params p;
-  p.lambda = lambda; p.L = L; p.precision = precision; p.nonneg = 0; p.power_iters = 30; p.pair_state = 0;
-  p.x0 = nullptr; p.v0 = nullptr;
-  const int rc0 = validate_problem(Bobs, m, n, A, B, r, &p);
-  if (rc0 != SFISTA_OK) return rc0;
-  sfista_diff* d = new (std::nothrow) sfista_diff();
-  if (!d) return set_error(SFISTA_ERR_NOMEM, "host allocation failed");
-  sfista_handle h = nullptr;
-  int rc = sfista_setup(Bobs, m, n, A, B, r, &p, stream, &h);
-  if (rc != SFISTA_OK) {
-    delete d;
-    return rc;
-  }
-  d->p = h;
-  d->iters = iters;
-  d->ckpt = ckpt_every;
-  d->nseg = (iters + ckpt_every - 1) / ckpt_every;
-  d->lam = lambda;
-  d->L = h->L;
-  const double sden = d->L + lambda * lambda;
-  d->c1 = d->L / sden;
-  d->c2 = 1.0 / sden;
-  d->beta.assign(iters + 2, 0.0);
-  double t = 1.0;
-  for (int k = 1; k <= iters + 1; ++k) {
-    const double tn = (1.0 + sqrt(1.0 + 4.0 * t * t)) / 2.0;
-    d->beta[k] = (t - 1.0) / tn;
-    t = tn;
-  }
-  rc = SFISTA_OK;
-  if (precision == SFISTA_FP64) rc = diff_setup_mode<M_F64>(d);
-  else rc = diff_setup_mode<M_F32>(d);
-  if (rc != SFISTA_OK) {
-    delete d;
-    return rc;
-  }
-  *out = d;
-  return SFISTA_OK;
-}
-
-int sfista_diff_forward(sfista_diff_handle d, double* X_out) {
-  clear_error();
-  if (!d) return set_error(SFISTA_ERR_ARG, "NULL handle");
-  hipError_t e = d->p->mode == M_F64 ? diff_forward_mode<M_F64>(d, X_out) : diff_forward_mode<M_F32>(d, X_out);
-  if (e != hipSuccess) return hip_fail(e, "sfista_diff_forward");
-  d->forward_done = true;
-  return SFISTA_OK;
-}
-
-int sfista_diff_backward(sfista_diff_handle d, const double* dX, double* dA, double* dB, double* dlambda) {
-  clear_error();
-  if (!d || !dX || !dA || !dB || !dlambda) return set_error(SFISTA_ERR_ARG, "NULL argument");
-  if (!d->forward_done) return set_error(SFISTA_ERR_ARG, "sfista_diff_backward needs a forward pass first");
-  hipError_t e = d->p->mode == M_F64 ? diff_backward_mode<M_F64>(d, dX, dA, dB, dlambda)
-                                     : diff_backward_mode<M_F32>(d, dX, dA, dB, dlambda);
-  if (e != hipSuccess) return hip_fail(e, "sfista_diff_backward");
-  if (!isfinite(*dlambda)) return set_error(SFISTA_ERR_NONFINITE, "lambda gradient is not finite");
-  return SFISTA_OK;
-}
-
-int sfista_diff_get_L(sfista_diff_handle d, double* L) {
-  clear_error();
-  if (!d || !L) return set_error(SFISTA_ERR_ARG, "NULL argument");
-  *L = d->L;
-  return SFISTA_OK;
-}
-
-void sfista_diff_destroy(sfista_diff_handle d) { delete d; }
 
 }  // extern "C"

@@ -95,9 +95,10 @@ def lib() -> ctypes.CDLL:
     L.sfista_batch_tiles.argtypes = [vp, ctypes.POINTER(i)]
     L.sfista_batch_destroy.argtypes = [vp]
     L.sfista_batch_destroy.restype = None
-    L.sfista_diff_setup.argtypes = [vp, i, i, vp, vp, i, d, d, i, i, i, vp, ctypes.POINTER(vp)]
-    L.sfista_diff_forward.argtypes = [vp, vp]
-    L.sfista_diff_backward.argtypes = [vp, vp, vp, vp, ctypes.POINTER(d)]
+    L.sfista_diff_setup.argtypes = [ctypes.POINTER(BatchItem), i, i, i, i, vp, ctypes.POINTER(vp)]
+    L.sfista_diff_forward.argtypes = [vp, ctypes.POINTER(vp)]
+    L.sfista_diff_backward.argtypes = [vp, ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.POINTER(vp),
+                                       ctypes.POINTER(d)]
     L.sfista_diff_get_L.argtypes = [vp, ctypes.POINTER(d)]
     L.sfista_diff_destroy.argtypes = [vp]
     L.sfista_diff_destroy.restype = None
@@ -281,47 +282,58 @@ class Batch:
 
 
 class Unrolled:
-    """Differentiable unrolled sFISTA for one image: ``forward()`` runs
-    ``iters`` iterations of Algorithm 2 from zero (``L`` fixed, checkpoints
-    every ``ckpt`` iterations) and returns X; ``backward(dX)`` returns
-    ``(dA, dB, dlam)``, the gradient of a loss whose derivative in X is dX.
-    ``precision`` is "fp32" or "fp64"."""
+    """Differentiable unrolled sFISTA for a batch of problems of one rank r:
+    ``forward()`` runs ``iters`` iterations of Algorithm 2 from zero on every
+    problem (each ``L`` fixed, checkpoints every ``ckpt`` iterations) and
+    returns the list of X; ``backward(dXs)`` returns ``(dAs, dBs, dlams)``,
+    the gradients of a loss whose derivative in each X is the matching dX.
+    ``problems`` is a sequence of ``(Bobs, A, B, lam, L)`` with float64 device
+    tensors (``L`` None: power estimate).  ``precision`` is "fp32" or "fp64"."""
 
-    def __init__(self, Bobs, A, B, lam: float, L: Optional[float] = None, iters: int = 50, ckpt: int = 10,
-                 precision: str = "fp32", stream=None):
-        m, n = Bobs.shape
-        r = A.shape[0]
-        if A.shape != (r, n, n) or B.shape != (r, m, m):
-            raise ValueError("A must be (r, n, n) and B (r, m, m) for Bobs of shape (m, n)")
+    def __init__(self, problems, iters: int = 50, ckpt: int = 10, precision: str = "fp32", stream=None):
+        cnt = len(problems)
+        items = (BatchItem * max(cnt, 1))()
+        self.shapes, self.ranks, self.device = [], [], None
+        for k, (Bobs, A, B, lam, L) in enumerate(problems):
+            m, n = Bobs.shape
+            r = A.shape[0]
+            if A.shape != (r, n, n) or B.shape != (r, m, m):
+                raise ValueError(f"problem {k}: A must be (r, n, n) and B (r, m, m) for Bobs of shape (m, n)")
+            items[k] = BatchItem(_dev_f64(Bobs, "Bobs"), m, n, _dev_f64(A, "A"), _dev_f64(B, "B"), r,
+                                 float(lam), float(L) if L is not None else 0.0)
+            self.shapes.append((m, n))
+            self.ranks.append(r)
+            self.device = Bobs.device
         self._h = None
-        self.shape, self.r, self.device = (m, n), r, Bobs.device
         h = ctypes.c_void_p()
-        _check(lib().sfista_diff_setup(_dev_f64(Bobs, "Bobs"), m, n, _dev_f64(A, "A"), _dev_f64(B, "B"), r,
-                                       float(lam), float(L) if L is not None else 0.0, PRECISIONS[precision],
-                                       int(iters), int(ckpt), _stream(stream), ctypes.byref(h)))
+        _check(lib().sfista_diff_setup(items, cnt, PRECISIONS[precision], int(iters), int(ckpt), _stream(stream),
+                                       ctypes.byref(h)))
         self._h = h
 
     @property
-    def L(self) -> float:
-        v = ctypes.c_double()
-        _check(lib().sfista_diff_get_L(self._h, ctypes.byref(v)))
-        return v.value
+    def L(self):
+        v = (ctypes.c_double * len(self.shapes))()
+        _check(lib().sfista_diff_get_L(self._h, v))
+        return list(v)
 
     def forward(self):
         import torch
-        X = torch.empty(self.shape, dtype=torch.float64, device=self.device)
-        _check(lib().sfista_diff_forward(self._h, X.data_ptr()))
-        return X
+        xs = [torch.empty(s, dtype=torch.float64, device=self.device) for s in self.shapes]
+        ptrs = (ctypes.c_void_p * len(xs))(*[x.data_ptr() for x in xs])
+        _check(lib().sfista_diff_forward(self._h, ptrs))
+        return xs
 
-    def backward(self, dX):
+    def backward(self, dXs):
         import torch
-        m, n = self.shape
-        dA = torch.empty((self.r, n, n), dtype=torch.float64, device=self.device)
-        dB = torch.empty((self.r, m, m), dtype=torch.float64, device=self.device)
-        dlam = ctypes.c_double()
-        _check(lib().sfista_diff_backward(self._h, _dev_f64(dX.contiguous(), "dX"), dA.data_ptr(), dB.data_ptr(),
-                                          ctypes.byref(dlam)))
-        return dA, dB, dlam.value
+        cnt = len(self.shapes)
+        dXs = [_contig_f64(x, "dX") for x in dXs]
+        dA = [torch.empty((r, n, n), dtype=torch.float64, device=self.device) for (m, n), r in zip(self.shapes, self.ranks)]
+        dB = [torch.empty((r, m, m), dtype=torch.float64, device=self.device) for (m, n), r in zip(self.shapes, self.ranks)]
+        P = ctypes.c_void_p * cnt
+        dl = (ctypes.c_double * cnt)()
+        _check(lib().sfista_diff_backward(self._h, P(*[x.data_ptr() for x in dXs]), P(*[a.data_ptr() for a in dA]),
+                                          P(*[b.data_ptr() for b in dB]), dl))
+        return dA, dB, list(dl)
 
     def close(self):
         if self._h is not None:
@@ -335,13 +347,11 @@ class Unrolled:
             pass
 
 
-def _map_threads(fn, count):
-    """fn(0..count-1) on host threads (the library calls release the GIL), in order."""
-    if count == 1:
-        return [fn(0)]
-    from concurrent.futures import ThreadPoolExecutor
-    with ThreadPoolExecutor(max_workers=min(count, 16)) as ex:
-        return list(ex.map(fn, range(count)))
+def _contig_f64(t, name):
+    import torch
+    t = t.to(torch.float64).contiguous()
+    _dev_f64(t, name)
+    return t
 
 
 def _unrolled_function():
@@ -355,60 +365,28 @@ def _unrolled_function():
         @staticmethod
         def forward(ctx, A, B, lam, Bobs, L, iters, ckpt, precision):
             N = Bobs.shape[0]
+            lams = lam.detach().reshape(-1).expand(N).tolist()
             if L is None:
                 Ls = [None] * N
             else:
                 Lv = [float(v) for v in np.asarray(L.detach().cpu() if isinstance(L, torch.Tensor) else L,
                                                    dtype=np.float64).reshape(-1)]
                 Ls = Lv * N if len(Lv) == 1 else Lv
-            lams = lam.detach().reshape(-1).expand(N).tolist()
-            streams = [torch.cuda.Stream(device=Bobs.device) for _ in range(N)]
-            cur = torch.cuda.current_stream(Bobs.device)
-            for k in range(N):
-                streams[k].wait_stream(cur)
             Ad, Bd, Od = A.detach(), B.detach(), Bobs.detach()
-
-            def one(k):   # each image on its own stream, driven from its own host thread
-                with torch.cuda.stream(streams[k]):
-                    u = Unrolled(Od[k].contiguous(), Ad[k].contiguous(), Bd[k].contiguous(), lams[k], Ls[k], iters,
-                                 ckpt, precision, stream=streams[k])
-                    return u, u.forward()
-
-            res = _map_threads(one, N)
-            for k in range(N):
-                cur.wait_stream(streams[k])
-                res[k][1].record_stream(cur)   # made on stream k, consumed on the caller's stream
-            ctx.plans = [u for u, _ in res]
-            ctx.streams = streams
+            u = Unrolled([(Od[k].contiguous(), Ad[k].contiguous(), Bd[k].contiguous(), lams[k], Ls[k])
+                          for k in range(N)], iters, ckpt, precision)
+            X = torch.stack(u.forward())
+            ctx.plan = u
             ctx.lam_shape = lam.shape
-            return torch.stack([x for _, x in res])
+            return X
 
         @staticmethod
         def backward(ctx, dX):
             N = dX.shape[0]
-            dXd = dX.to(torch.float64).contiguous()
-            cur = torch.cuda.current_stream(dX.device)
-            for st in ctx.streams:
-                st.wait_stream(cur)
-
-            def one(k):
-                with torch.cuda.stream(ctx.streams[k]):
-                    return ctx.plans[k].backward(dXd[k])
-
-            res = _map_threads(one, N)
-            for st in ctx.streams:
-                cur.wait_stream(st)
-            for a, b, _ in res:
-                a.record_stream(cur)
-                b.record_stream(cur)
-            dA = [a for a, _, _ in res]
-            dB = [b for _, b, _ in res]
-            dl = [l for _, _, l in res]
-            for u in ctx.plans:
-                u.close()
+            dA, dB, dl = ctx.plan.backward([dX[k] for k in range(N)])
+            ctx.plan.close()
             dlam = torch.tensor(dl, dtype=torch.float64, device=dX.device)
-            dlam = dlam.sum().reshape(ctx.lam_shape) if len(ctx.lam_shape) == 0 or ctx.lam_shape.numel() == 1 \
-                else dlam.reshape(ctx.lam_shape)
+            dlam = dlam.sum().reshape(ctx.lam_shape) if ctx.lam_shape.numel() == 1 else dlam.reshape(ctx.lam_shape)
             return torch.stack(dA), torch.stack(dB), dlam, None, None, None, None, None
 
     return SfistaUnrolledFn

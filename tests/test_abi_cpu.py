@@ -137,24 +137,32 @@ def test_batch_calls_reject_null(L):
     (dict(precision=4), -2),          # BF16X3 is not offered in the differentiable form
     (dict(iters=0), -1),
     (dict(ckpt=0), -1),
+    (dict(count=0), -1),
     (dict(m=0), -1),
-    (dict(r=7, m=4, n=4), -1),
-    (dict(lam=-1.0), -1),
+    (dict(r=9), -1),                  # r > min(m, n) in the last problem
+    (dict(lambda_=-1.0), -1),
+    (dict(r2=2), -2),                 # ranks differ between problems
 ])
 def test_diff_setup_rejects_invalid_arguments(L, args, expect):
-    a = dict(m=4, n=4, r=1, lam=0.1, Lc=1.0, precision=1, iters=5, ckpt=2)
-    a.update(args)
+    a = dict(precision=1, iters=5, ckpt=2, count=2)
+    a.update({k: v for k, v in args.items() if k in a})
+    item = {k: v for k, v in args.items() if k in ("m", "r", "lambda_")}
+    items = _items(2, **item)
+    if "r2" in args:
+        items[0].r = 1
+        items[1].r = args["r2"]
     h = ctypes.c_void_p()
-    rc = L.sfista_diff_setup(FAKE, a["m"], a["n"], FAKE, FAKE, a["r"], a["lam"], a["Lc"], a["precision"],
-                             a["iters"], a["ckpt"], None, ctypes.byref(h))
+    rc = L.sfista_diff_setup(items, a["count"], a["precision"], a["iters"], a["ckpt"], None, ctypes.byref(h))
     assert rc == expect
     assert h.value is None
 
 
 def test_diff_calls_reject_null(L):
-    d = ctypes.c_double()
-    assert L.sfista_diff_setup(FAKE, 4, 4, FAKE, FAKE, 1, 0.1, 1.0, 1, 5, 2, None, None) == -1
+    d = (ctypes.c_double * 2)()
+    P = ctypes.c_void_p * 2
+    assert L.sfista_diff_setup(_items(), 2, 1, 5, 2, None, None) == -1
+    assert L.sfista_diff_setup(None, 2, 1, 5, 2, None, ctypes.byref(ctypes.c_void_p())) == -1
     assert L.sfista_diff_forward(None, None) == -1
-    assert L.sfista_diff_backward(None, FAKE, FAKE, FAKE, ctypes.byref(d)) == -1
-    assert L.sfista_diff_get_L(None, ctypes.byref(d)) == -1
+    assert L.sfista_diff_backward(None, P(), P(), P(), d) == -1
+    assert L.sfista_diff_get_L(None, d) == -1
     L.sfista_diff_destroy(None)

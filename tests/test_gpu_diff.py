@@ -37,12 +37,12 @@ def _small(m=48, n=40, r=3, seed=21):
 
 
 def _gpu_grad(sf, K, H, B, x, lam, L, iters, ckpt, precision):
-    u = sf.Unrolled(dev(B), dev(K), dev(H), lam, L=L, iters=iters, ckpt=ckpt, precision=precision)
-    X = u.forward()
+    u = sf.Unrolled([(dev(B), dev(K), dev(H), lam, L)], iters=iters, ckpt=ckpt, precision=precision)
+    X = u.forward()[0]
     dX = 2.0 * (X - dev(x)) / X.numel()
-    dA, dB, dlam = u.backward(dX)
+    dA, dB, dlam = u.backward([dX])
     u.close()
-    return host(X), host(dA), host(dB), dlam
+    return host(X), host(dA[0]), host(dB[0]), dlam[0]
 
 
 @pytest.mark.parametrize("iters,ckpt", [(1, 10), (25, 10), (12, 4)])
@@ -124,3 +124,22 @@ def test_autograd_batch(sf):
         assert rel(host(B.grad[t]), oH) < 1e-10
         tot += olam
     assert abs(lam.grad.item() - tot) <= 1e-10 * abs(tot)
+
+
+def test_uneven_batch_matches_single_images(sf):
+    """Problems of different sizes (one rank) in one handle: each gradient
+    equals the oracle's for that problem alone."""
+    cases = [_small(m=40, n=56, r=2, seed=31), _small(m=64, n=64, r=2, seed=32), _small(m=72, n=48, r=2, seed=33)]
+    lams = [0.12, 0.2, 0.08]
+    u = sf.Unrolled([(dev(B), dev(K), dev(H), lam, L) for (K, H, B, x, L), lam in zip(cases, lams)],
+                    iters=13, ckpt=5, precision="fp64")
+    Xs = u.forward()
+    dXs = [2.0 * (X - dev(c[3])) / X.numel() for X, c in zip(Xs, cases)]
+    dA, dB, dl = u.backward(dXs)
+    u.close()
+    for (K, H, B, x, L), lam, X, a, b, l in zip(cases, lams, Xs, dA, dB, dl):
+        _, oK, oH, olam = O.sfista64_grad(K, H, B, lam, L, 13, x)
+        say(f"[diff uneven] {B.shape}: dA {rel(host(a), oK):.2e} dB {rel(host(b), oH):.2e}")
+        assert rel(host(X), O.sfista64(K, H, B, lam, L, 13)) < 1e-12
+        assert rel(host(a), oK) < 1e-10 and rel(host(b), oH) < 1e-10
+        assert abs(l - olam) <= 1e-10 * abs(olam)
