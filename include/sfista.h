@@ -21,7 +21,10 @@
  *   - calls return SFISTA_OK (0) or a negative sfista_status; no exception or
  *     abort crosses the ABI; sfista_last_error() gives a message for the
  *     calling thread's last failure;
- *   - arguments are validated on the host before any device work starts.
+ *   - arguments are validated on the host before any device work starts;
+ *   - the library's own device buffers come from a memory pool of its own,
+ *     one per device; freed buffers stay cached there (at most 8 GiB per
+ *     device) for the next handle until sfista_release_cached() is called.
  */
 #ifndef SFISTA_H
 #define SFISTA_H
@@ -229,6 +232,16 @@ typedef struct sfista_diff* sfista_diff_handle;
 int sfista_diff_setup(const sfista_batch_item* items, int count, int precision, int iters, int ckpt_every,
                       hipStream_t stream, sfista_diff_handle* out);
 
+/* Load new problems into the handle: `count` items of the same sizes and
+ * rank as at setup, in the same order (new Bobs, factors, lambda; L <= 0
+ * estimates L again).  No device memory is allocated, except once for the
+ * start vector of the first estimate of L; a training loop sets up once and
+ * updates before each forward pass.  Items are validated before anything
+ * changes; a failure later (a HIP error, a non-finite estimate) leaves the
+ * handle to be updated again or destroyed.  A forward pass must follow
+ * before the next backward pass. */
+int sfista_diff_update(sfista_diff_handle h, const sfista_batch_item* items, int count);
+
 /* Forward pass: X_out[b] (m x n, FP64, entries nullable, or X_out NULL)
  * receives X_iters of problem b.  May be called again (it restarts from 0). */
 int sfista_diff_forward(sfista_diff_handle h, double* const* X_out);
@@ -249,6 +262,11 @@ int sfista_get_L(sfista_handle h, double* L);
 
 /* Release the plan and its device buffers (synchronises its stream). */
 void sfista_destroy(sfista_handle h);
+
+/* Hand the device memory cached by the library's pools (freed buffers of
+ * destroyed handles) back to the system.  Buffers of live handles are not
+ * affected; call it when no library work is in flight. */
+int sfista_release_cached(void);
 
 /* Message describing the calling thread's last failure ("" if none). */
 const char* sfista_last_error(void);

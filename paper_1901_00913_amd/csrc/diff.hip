@@ -218,6 +218,33 @@ namespace {
 //   ep[2]: EpiResid  index 0 = forward, 1 + t = recomputation, 1 + C + t = adjoint
 //   ep[3]: EpiStack  index 0 = forward, 1 + t = recomputation, 1 + C + t = adjoint
 //   ep[4]: EpiUpd64  index k - 1, then EpiYbar after them (see ybar_base)
+// The per-iteration update (EpiUpd64) and Ybar (EpiYbar) epilogues: the only
+// tables that depend on lambda and L.
+template <int MODE>
+void fill_step_tables(const sfista_diff* d, std::vector<EpiUpd64<MODE>>& eu, std::vector<EpiYbar<MODE>>& ey) {
+  const int cnt = d->count, C = d->ckpt, K = d->iters;
+  eu.assign((size_t)K * cnt, EpiUpd64<MODE>{});
+  ey.assign((size_t)K * cnt, EpiYbar<MODE>{});
+  for (int b = 0; b < cnt; ++b) {
+    const sfista_plan* h = d->plans[b];
+    const DiffImg& im = d->img[b];
+    const int n = h->n;
+    const long mn = (long)h->m * n;
+    for (int k = 1; k <= K; ++k) {
+      const int t = (k - 1) % C + 1;   // position of k in its segment
+      EpiUpd64<MODE>& e = eu[(size_t)(k - 1) * cnt + b];
+      e.y[0] = h->Y[0]; e.y[1] = h->Y[1]; e.ldy = h->ldY;
+      e.yin = im.ys + (long)(t - 1) * mn;
+      e.xprev = im.xs + (long)t * mn;
+      e.xout = im.xs + (long)(t + 1) * mn;
+      e.ynext = im.ys + (long)t * mn;
+      e.n = n; e.c1 = d->L[b] / (d->L[b] + d->lam[b] * d->lam[b]); e.c2 = im.c2; e.beta = d->beta[k];
+      EpiYbar<MODE>& y = ey[(size_t)(k - 1) * cnt + b];
+      y.ybar = im.yb[k % 3]; y.xbar = im.xbar; y.n = n; y.c1 = e.c1;
+    }
+  }
+}
+
 template <int MODE>
 int diff_build(sfista_diff* d) {
   using TB = typename BigTile<MODE>::T;
@@ -271,8 +298,8 @@ int diff_build(sfista_diff* d) {
   // epilogue tables
   std::vector<EpiStack<MODE>> e0((1 + C) * cnt), e1(C * cnt), e3((1 + 2 * C) * cnt);
   std::vector<EpiResid<MODE>> e2((1 + 2 * C) * cnt);
-  std::vector<EpiUpd64<MODE>> eu((size_t)K * cnt);
-  std::vector<EpiYbar<MODE>> ey((size_t)K * cnt);
+  std::vector<EpiUpd64<MODE>> eu;
+  std::vector<EpiYbar<MODE>> ey;
   for (int b = 0; b < cnt; ++b) {
     sfista_plan* h = d->plans[b];
     const DiffImg& im = d->img[b];
@@ -304,19 +331,8 @@ int diff_build(sfista_diff* d) {
       EpiStack<MODE>& sa = e3[(1 + C + t) * cnt + b];   // W_k -> AA slot (2t + 1)
       stack(sa, false); sa.g[0] = im.AA[0]; sa.g[1] = im.AA[1]; sa.ldg = im.ldAA; sa.koff = (2L * t + 1) * m;
     }
-    for (int k = 1; k <= K; ++k) {
-      const int t = (k - 1) % C + 1;   // position of k in its segment
-      EpiUpd64<MODE>& e = eu[(size_t)(k - 1) * cnt + b];
-      e.y[0] = h->Y[0]; e.y[1] = h->Y[1]; e.ldy = h->ldY;
-      e.yin = im.ys + (long)(t - 1) * mn;
-      e.xprev = im.xs + (long)t * mn;
-      e.xout = im.xs + (long)(t + 1) * mn;
-      e.ynext = im.ys + (long)t * mn;
-      e.n = n; e.c1 = d->L[b] / (d->L[b] + d->lam[b] * d->lam[b]); e.c2 = im.c2; e.beta = d->beta[k];
-      EpiYbar<MODE>& y = ey[(size_t)(k - 1) * cnt + b];
-      y.ybar = im.yb[k % 3]; y.xbar = im.xbar; y.n = n; y.c1 = e.c1;
-    }
   }
+  fill_step_tables<MODE>(d, eu, ey);
   d->ep[0] = upload(e0.data(), sizeof(e0[0]) * e0.size());
   d->ep[1] = upload(e1.data(), sizeof(e1[0]) * e1.size());
   d->ep[2] = upload(e2.data(), sizeof(e2[0]) * e2.size());
@@ -357,6 +373,18 @@ hipError_t diff_iteration(sfista_diff* d, int k, int t, bool grad) {
   if ((e = product<MODE, EpiResid<MODE>>(d, 2, 2, grad ? t : 0)) != hipSuccess) return e;
   if ((e = product<MODE, EpiStack<MODE>>(d, 3, 3, grad ? t : 0)) != hipSuccess) return e;
   return product<MODE, EpiUpd64<MODE>>(d, 4, 4, k - 1);
+}
+
+// New lambda and L: per-image constants and the tables that hold them.
+template <int MODE>
+hipError_t diff_refresh_tables(sfista_diff* d) {
+  std::vector<EpiUpd64<MODE>> eu;
+  std::vector<EpiYbar<MODE>> ey;
+  fill_step_tables<MODE>(d, eu, ey);
+  hipError_t e = hipMemcpyAsync(d->ep[4], eu.data(), sizeof(eu[0]) * eu.size(), hipMemcpyHostToDevice, d->s);
+  if (e == hipSuccess) e = hipMemcpyAsync(d->ep[5], ey.data(), sizeof(ey[0]) * ey.size(), hipMemcpyHostToDevice, d->s);
+  if (e == hipSuccess) e = hipStreamSynchronize(d->s);   // the host tables die here
+  return e;
 }
 
 template <int MODE>
@@ -500,8 +528,8 @@ int sfista_diff_setup(const sfista_batch_item* items, int count, int precision, 
     sfista_params p{};
     p.lambda = items[i].lambda; p.L = items[i].L; p.precision = precision; p.power_iters = 30; p.pair_state = 0;
     sfista_handle h = nullptr;
-    const int rc = sfista_setup(items[i].Bobs, items[i].m, items[i].n, items[i].A, items[i].B, items[i].r, &p, stream,
-                                &h);
+    const int rc =
+        plan_create(items[i].Bobs, items[i].m, items[i].n, items[i].A, items[i].B, items[i].r, &p, stream, &d->arena, &h);
     if (rc != SFISTA_OK) {
       std::string msg = last_error_slot();
       delete d;
@@ -524,6 +552,40 @@ int sfista_diff_setup(const sfista_batch_item* items, int count, int precision, 
     return rc;
   }
   *out = d;
+  return SFISTA_OK;
+}
+
+int sfista_diff_update(sfista_diff_handle d, const sfista_batch_item* items, int count) {
+  clear_error();
+  if (!d || !items) return set_error(SFISTA_ERR_ARG, "NULL argument");
+  if (count != d->count) return set_error(SFISTA_ERR_ARG, "count %d differs from the handle's %d", count, d->count);
+  for (int i = 0; i < count; ++i) {
+    const sfista_plan* h = d->plans[i];
+    if (items[i].m != h->m || items[i].n != h->n || items[i].r != h->r)
+      return set_error(SFISTA_ERR_ARG, "problem %d: size %d x %d, rank %d differ from the handle's %d x %d, %d", i,
+                       items[i].m, items[i].n, items[i].r, h->m, h->n, h->r);
+    sfista_params p{};
+    p.lambda = items[i].lambda; p.L = items[i].L; p.precision = d->mode; p.power_iters = 30;
+    const int rc = validate_problem(items[i].Bobs, items[i].m, items[i].n, items[i].A, items[i].B, items[i].r, &p);
+    if (rc != SFISTA_OK) {
+      std::string msg = last_error_slot();
+      return set_error(rc, "problem %d: %s", i, msg.c_str());
+    }
+  }
+  d->forward_done = false;
+  for (int i = 0; i < count; ++i) {
+    sfista_plan* h = d->plans[i];
+    const int rc = plan_refresh(h, items[i].Bobs, items[i].A, items[i].B, items[i].lambda, items[i].L);
+    if (rc != SFISTA_OK) {
+      std::string msg = last_error_slot();
+      return set_error(rc, "problem %d: %s", i, msg.c_str());
+    }
+    d->lam[i] = items[i].lambda;
+    d->L[i] = h->L;
+    d->img[i].c2 = 1.0 / (h->L + items[i].lambda * items[i].lambda);
+  }
+  const hipError_t e = d->mode == M_F64 ? diff_refresh_tables<M_F64>(d) : diff_refresh_tables<M_F32>(d);
+  if (e != hipSuccess) return hip_fail(e, "sfista_diff_update");
   return SFISTA_OK;
 }
 

@@ -29,6 +29,7 @@ struct sfista_plan {
   void* st[2] = {};
   double* aux = nullptr;      // m x n FP64 scratch (power iterate, copies)
   double* red = nullptr;      // reduction partials [RED_BLOCKS] + scalars
+  double* v0buf = nullptr;    // m x n start of the power iteration (made on first use)
   void* ws = nullptr;         // K-split partials of the planned products
   sf::GemmPlanDev pl[4];      // work lists of F1, F2, G1, G2
   double bobs_norm = 0.0;
@@ -40,7 +41,8 @@ struct sfista_plan {
   hipEvent_t mid_ev = nullptr;                     // recorded between a GEMM and its split reduction
   double t_sum[8] = {0, 0, 0, 0, 0, 0, 0, 0};      // GEMM kernels 0..3, their reductions 4..7
   long t_cnt[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-  sf::DeviceArena arena;
+  sf::DeviceArena own_arena;
+  sf::DeviceArena* mem = &own_arena;   // the owner's arena when the plan is part of a multi-image handle
   ~sfista_plan() {
     for (hipEvent_t e : ev_pool) (void)hipEventDestroy(e);
   }
@@ -101,5 +103,16 @@ inline int validate_problem(const double* Bobs, int m, int n, const double* A, c
   if (p->power_iters < 0) return set_error(SFISTA_ERR_ARG, "power_iters must be >= 0");
   return SFISTA_OK;
 }
+
+// Validates and sets up one problem (the work of sfista_setup).  With
+// `shared` non-null the plan's device buffers come from that arena, which
+// has to outlive the plan.
+int plan_create(const double* Bobs, int m, int n, const double* A, const double* B, int r, const sfista_params* p,
+                hipStream_t stream, DeviceArena* shared, sfista_plan** out);
+
+// Loads a new problem of the plan's sizes and rank into an existing plan:
+// factors, observation, lambda, L (estimated again when L <= 0) and X_0 = 0.
+// Allocates nothing after the first estimate of L; synchronises the stream.
+int plan_refresh(sfista_plan* h, const double* Bobs, const double* A, const double* B, double lambda, double L);
 
 }  // namespace sf

@@ -188,6 +188,9 @@ hipError_t run_pack(sfista_plan* h, const double* A, const double* B) {
 }
 
 template <int MODE>
+int load_problem(sfista_plan* h, const double* Bobs, const double* A, const double* B, const sfista_params* p);
+
+template <int MODE>
 int setup_mode(sfista_plan* h, const double* Bobs, const double* A, const double* B, const sfista_params* p) {
   using Acc = typename ModeTraits<MODE>::Acc;
   constexpr int P = ModeTraits<MODE>::planes;
@@ -198,7 +201,7 @@ int setup_mode(sfista_plan* h, const double* Bobs, const double* A, const double
   h->ldY = ld_of(n);  h->ldT = ld_of(rm);  h->ldR = ld_of(m);  h->ldS = ld_of(rn);
   auto planes = [&](void** dst, long rows, long ld) -> bool {
     for (int q = 0; q < P; ++q) {
-      dst[q] = h->arena.alloc_zero((size_t)rows_of(rows) * ld * es, h->s);
+      dst[q] = h->mem->alloc_zero((size_t)rows_of(rows) * ld * es, h->s);
       if (!dst[q]) return false;
     }
     return true;
@@ -207,11 +210,11 @@ int setup_mode(sfista_plan* h, const double* Bobs, const double* A, const double
             planes(h->At, n, h->ldAt) && planes(h->Y, m, h->ldY) && planes(h->T, n, h->ldT) &&
             planes(h->R, n, h->ldR) && planes(h->S, m, h->ldS) && planes(h->Xop, m, h->ldY);
   const size_t st_bytes = (size_t)m * n * (h->kind == ST_F32 ? 4 : 8);
-  ok = ok && (h->bobs_t = h->arena.alloc_zero((size_t)m * n * sizeof(Acc), h->s)) &&
-       (h->st[0] = h->arena.alloc_zero(st_bytes, h->s)) && (h->st[1] = h->arena.alloc_zero(st_bytes, h->s)) &&
-       (h->aux = static_cast<double*>(h->arena.alloc_zero((size_t)m * n * 8, h->s))) &&
-       (h->red = static_cast<double*>(h->arena.alloc_zero((RED_BLOCKS + 8) * 8, h->s)));
-  if (!ok) return set_error(SFISTA_ERR_NOMEM, "device allocation failed (%s)", h->arena.last_error());
+  ok = ok && (h->bobs_t = h->mem->alloc_zero((size_t)m * n * sizeof(Acc), h->s)) &&
+       (h->st[0] = h->mem->alloc_zero(st_bytes, h->s)) && (h->st[1] = h->mem->alloc_zero(st_bytes, h->s)) &&
+       (h->aux = static_cast<double*>(h->mem->alloc_zero((size_t)m * n * 8, h->s))) &&
+       (h->red = static_cast<double*>(h->mem->alloc_zero((RED_BLOCKS + 8) * 8, h->s)));
+  if (!ok) return set_error(SFISTA_ERR_NOMEM, "device allocation failed (%s)", h->mem->last_error());
 
   // work lists of the four products (tile order, K splits of the last round)
   {
@@ -229,12 +232,12 @@ int setup_mode(sfista_plan* h, const double* Bobs, const double* A, const double
     for (int q = 0; q < 4; ++q) {
       const GemmPlan& gp = plans[q];
       GemmPlanDev& pd = h->pl[q];
-      PlanItem* items = static_cast<PlanItem*>(h->arena.alloc_zero(gp.items.size() * sizeof(PlanItem), h->s));
+      PlanItem* items = static_cast<PlanItem*>(h->mem->alloc_zero(gp.items.size() * sizeof(PlanItem), h->s));
       int2* tiles = gp.split_tiles.empty()
                         ? nullptr
-                        : static_cast<int2*>(h->arena.alloc_zero(gp.split_tiles.size() * sizeof(int2), h->s));
+                        : static_cast<int2*>(h->mem->alloc_zero(gp.split_tiles.size() * sizeof(int2), h->s));
       if (!items || (!gp.split_tiles.empty() && !tiles))
-        return set_error(SFISTA_ERR_NOMEM, "device allocation failed (%s)", h->arena.last_error());
+        return set_error(SFISTA_ERR_NOMEM, "device allocation failed (%s)", h->mem->last_error());
       if (hipMemcpyAsync(items, gp.items.data(), gp.items.size() * sizeof(PlanItem), hipMemcpyHostToDevice, h->s) !=
               hipSuccess ||
           (tiles && hipMemcpyAsync(tiles, gp.split_tiles.data(), gp.split_tiles.size() * sizeof(int2),
@@ -248,10 +251,19 @@ int setup_mode(sfista_plan* h, const double* Bobs, const double* A, const double
       pd.kchunk = gp.kchunk;
       ws_elems = std::max(ws_elems, gp.ws_elems() * TB::BM * TB::BN);
     }
-    if (ws_elems > 0 && !(h->ws = h->arena.alloc_zero(ws_elems * sizeof(Acc), h->s)))
-      return set_error(SFISTA_ERR_NOMEM, "device allocation failed (%s)", h->arena.last_error());
+    if (ws_elems > 0 && !(h->ws = h->mem->alloc_zero(ws_elems * sizeof(Acc), h->s)))
+      return set_error(SFISTA_ERR_NOMEM, "device allocation failed (%s)", h->mem->last_error());
   }
 
+  return load_problem<MODE>(h, Bobs, A, B, p);
+}
+
+// Packs the factors, stores Bobs^T, takes ||Bobs||, estimates L unless h->L
+// is set, and sets X_0; synchronises the stream.
+template <int MODE>
+int load_problem(sfista_plan* h, const double* Bobs, const double* A, const double* B, const sfista_params* p) {
+  using Acc = typename ModeTraits<MODE>::Acc;
+  const int m = h->m, n = h->n;
   hipError_t e;
   if ((e = run_pack<MODE>(h, A, B)) != hipSuccess) return hip_fail(e, "factor packing");
   {
@@ -270,11 +282,11 @@ int setup_mode(sfista_plan* h, const double* Bobs, const double* A, const double
     const double* v0 = p->v0;
     if (!v0) {
       // fixed internal start: a deterministic hash pattern
-      void* tmp = h->arena.alloc_zero((size_t)m * n * 8, h->s);
-      if (!tmp) return set_error(SFISTA_ERR_NOMEM, "device allocation failed");
-      hipLaunchKernelGGL(hash_fill_kernel, dim3(EW_BLOCKS), dim3(EW_THREADS), 0, h->s, static_cast<double*>(tmp),
-                         (long)m * n, 0x5f15a7ull);
-      v0 = static_cast<const double*>(tmp);
+      if (!h->v0buf && !(h->v0buf = static_cast<double*>(h->mem->alloc_zero((size_t)m * n * 8, h->s))))
+        return set_error(SFISTA_ERR_NOMEM, "device allocation failed");
+      hipLaunchKernelGGL(hash_fill_kernel, dim3(EW_BLOCKS), dim3(EW_THREADS), 0, h->s, h->v0buf, (long)m * n,
+                         0x5f15a7ull);
+      v0 = h->v0buf;
     }
     double L = 0.0;
     if ((e = run_power<MODE>(h, v0, steps, &L)) != hipSuccess) return hip_fail(e, "power iteration");
@@ -338,19 +350,15 @@ hipError_t apply_mode(sfista_plan* h, const double* X, double* AX, double* AtAX)
 
 }  // namespace
 
-// ====================================================================== C ABI
+namespace sf {
 
-extern "C" {
-
-int sfista_setup(const double* Bobs, int m, int n, const double* A, const double* B, int r,
-                 const sfista_params* p, hipStream_t stream, sfista_handle* out) {
-  clear_error();
-  if (!out) return set_error(SFISTA_ERR_ARG, "out handle pointer is NULL");
-  *out = nullptr;
+int plan_create(const double* Bobs, int m, int n, const double* A, const double* B, int r, const sfista_params* p,
+                hipStream_t stream, DeviceArena* shared, sfista_plan** out) {
   const int rc0 = validate_problem(Bobs, m, n, A, B, r, p);
   if (rc0 != SFISTA_OK) return rc0;
   sfista_plan* h = new (std::nothrow) sfista_plan();
   if (!h) return set_error(SFISTA_ERR_NOMEM, "host allocation failed");
+  if (shared) h->mem = shared;
   h->m = m; h->n = n; h->r = r; h->mode = p->precision; h->nonneg = p->nonneg ? 1 : 0;
   h->kind = state_kind(h->mode, p->pair_state);
   h->lam = p->lambda; h->L = p->L > 0.0 ? p->L : 0.0; h->s = stream;
@@ -363,6 +371,32 @@ int sfista_setup(const double* Bobs, int m, int n, const double* A, const double
   }
   *out = h;
   return SFISTA_OK;
+}
+
+int plan_refresh(sfista_plan* h, const double* Bobs, const double* A, const double* B, double lambda, double L) {
+  sfista_params p{};
+  p.lambda = lambda; p.L = L; p.precision = h->mode; p.power_iters = 30; p.nonneg = h->nonneg;
+  const int rc0 = validate_problem(Bobs, h->m, h->n, A, B, h->r, &p);
+  if (rc0 != SFISTA_OK) return rc0;
+  h->lam = lambda; h->L = L > 0.0 ? L : 0.0;
+  h->iter = 0; h->tk = 1.0; h->beta_prev = 0.0;
+  int rc = SFISTA_OK;
+  SF_DISPATCH(h->mode, rc = load_problem<MD>(h, Bobs, A, B, &p));
+  return rc;
+}
+
+}  // namespace sf
+
+// ====================================================================== C ABI
+
+extern "C" {
+
+int sfista_setup(const double* Bobs, int m, int n, const double* A, const double* B, int r,
+                 const sfista_params* p, hipStream_t stream, sfista_handle* out) {
+  clear_error();
+  if (!out) return set_error(SFISTA_ERR_ARG, "out handle pointer is NULL");
+  *out = nullptr;
+  return plan_create(Bobs, m, n, A, B, r, p, stream, nullptr, out);
 }
 
 int sfista_step(sfista_handle h, int iters) {
@@ -479,6 +513,12 @@ void sfista_destroy(sfista_handle h) {
   delete h;
 }
 
+int sfista_release_cached(void) {
+  clear_error();
+  const hipError_t e = release_cached_pools();
+  return e == hipSuccess ? SFISTA_OK : hip_fail(e, "sfista_release_cached");
+}
+
 const char* sfista_last_error(void) { return last_error_slot().c_str(); }
 
 }  // extern "C"
@@ -513,6 +553,7 @@ struct sfista_batch {
     if (gexec) (void)hipGraphExecDestroy(gexec);
     if (graph) (void)hipGraphDestroy(graph);
     for (sfista_plan* p : plans) delete p;
+    arena.release();                // its frees are ordered on s
     if (s) (void)hipStreamDestroy(s);
   }
 };
@@ -784,7 +825,8 @@ int sfista_batch_setup(const sfista_batch_item* items, int count, const sfista_p
     p.lambda = items[i].lambda;
     p.L = items[i].L;
     sfista_handle h = nullptr;
-    const int rc = sfista_setup(items[i].Bobs, items[i].m, items[i].n, items[i].A, items[i].B, items[i].r, &p, b->s, &h);
+    const int rc =
+        plan_create(items[i].Bobs, items[i].m, items[i].n, items[i].A, items[i].B, items[i].r, &p, b->s, &b->arena, &h);
     if (rc != SFISTA_OK) {
       std::string msg = last_error_slot();
       delete b;

@@ -34,7 +34,7 @@ EXPORTS = ("kron_approx", "sfista_setup", "sfista_step", "sfista_solve", "sfista
            "sfista_set_timing", "sfista_kernel_times", "sfista_get_L", "sfista_destroy",
            "sfista_last_error", "sfista_batch_setup", "sfista_batch_solve", "sfista_batch_tiles",
            "sfista_batch_destroy", "sfista_diff_setup", "sfista_diff_forward", "sfista_diff_backward",
-           "sfista_diff_get_L", "sfista_diff_destroy")
+           "sfista_diff_get_L", "sfista_diff_destroy", "sfista_diff_update", "sfista_release_cached")
 
 BATCH_AUTOTUNE = 1
 BATCH_GRAPH = 2
@@ -96,21 +96,28 @@ def lib() -> ctypes.CDLL:
     L.sfista_batch_destroy.argtypes = [vp]
     L.sfista_batch_destroy.restype = None
     L.sfista_diff_setup.argtypes = [ctypes.POINTER(BatchItem), i, i, i, i, vp, ctypes.POINTER(vp)]
+    L.sfista_diff_update.argtypes = [vp, ctypes.POINTER(BatchItem), i]
     L.sfista_diff_forward.argtypes = [vp, ctypes.POINTER(vp)]
     L.sfista_diff_backward.argtypes = [vp, ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.POINTER(vp),
                                        ctypes.POINTER(d)]
     L.sfista_diff_get_L.argtypes = [vp, ctypes.POINTER(d)]
     L.sfista_diff_destroy.argtypes = [vp]
     L.sfista_diff_destroy.restype = None
+    L.sfista_release_cached.argtypes = []
     L.sfista_last_error.argtypes = []
     L.sfista_last_error.restype = ctypes.c_char_p
     for name in ("kron_approx", "sfista_setup", "sfista_step", "sfista_solve", "sfista_apply", "sfista_get_L",
                  "sfista_set_timing", "sfista_kernel_times", "sfista_batch_setup", "sfista_batch_solve",
                  "sfista_batch_tiles", "sfista_diff_setup", "sfista_diff_forward", "sfista_diff_backward",
-                 "sfista_diff_get_L"):
+                 "sfista_diff_get_L", "sfista_diff_update", "sfista_release_cached"):
         getattr(L, name).restype = ctypes.c_int
     _lib = L
     return L
+
+
+def release_cached():
+    """Return the device memory cached by the library's pools to the system."""
+    _check(lib().sfista_release_cached())
 
 
 def _check(rc: int):
@@ -291,9 +298,19 @@ class Unrolled:
     tensors (``L`` None: power estimate).  ``precision`` is "fp32" or "fp64"."""
 
     def __init__(self, problems, iters: int = 50, ckpt: int = 10, precision: str = "fp32", stream=None):
+        items, self.shapes, self.ranks, self.device = self._items(problems)
+        self.iters, self.ckpt, self.precision = int(iters), int(ckpt), precision
+        self._h = None
+        h = ctypes.c_void_p()
+        _check(lib().sfista_diff_setup(items, len(problems), PRECISIONS[precision], self.iters, self.ckpt,
+                                       _stream(stream), ctypes.byref(h)))
+        self._h = h
+
+    @staticmethod
+    def _items(problems):
         cnt = len(problems)
         items = (BatchItem * max(cnt, 1))()
-        self.shapes, self.ranks, self.device = [], [], None
+        shapes, ranks, device = [], [], None
         for k, (Bobs, A, B, lam, L) in enumerate(problems):
             m, n = Bobs.shape
             r = A.shape[0]
@@ -301,14 +318,18 @@ class Unrolled:
                 raise ValueError(f"problem {k}: A must be (r, n, n) and B (r, m, m) for Bobs of shape (m, n)")
             items[k] = BatchItem(_dev_f64(Bobs, "Bobs"), m, n, _dev_f64(A, "A"), _dev_f64(B, "B"), r,
                                  float(lam), float(L) if L is not None else 0.0)
-            self.shapes.append((m, n))
-            self.ranks.append(r)
-            self.device = Bobs.device
-        self._h = None
-        h = ctypes.c_void_p()
-        _check(lib().sfista_diff_setup(items, cnt, PRECISIONS[precision], int(iters), int(ckpt), _stream(stream),
-                                       ctypes.byref(h)))
-        self._h = h
+            shapes.append((m, n))
+            ranks.append(r)
+            device = Bobs.device
+        return items, shapes, ranks, device
+
+    def update(self, problems):
+        """Load new problems of the same sizes and ranks (same order) into the
+        handle without allocating: new factors, observations, lambda, L."""
+        items, shapes, ranks, _ = self._items(problems)
+        if shapes != self.shapes or ranks != self.ranks:
+            raise ValueError("update needs the sizes and ranks the handle was set up with")
+        _check(lib().sfista_diff_update(self._h, items, len(problems)))
 
     @property
     def L(self):
@@ -363,7 +384,7 @@ def _unrolled_function():
         adjoint (L and Bobs are constants)."""
 
         @staticmethod
-        def forward(ctx, A, B, lam, Bobs, L, iters, ckpt, precision):
+        def forward(ctx, A, B, lam, Bobs, L, iters, ckpt, precision, plan):
             N = Bobs.shape[0]
             lams = lam.detach().reshape(-1).expand(N).tolist()
             if L is None:
@@ -373,10 +394,15 @@ def _unrolled_function():
                                                    dtype=np.float64).reshape(-1)]
                 Ls = Lv * N if len(Lv) == 1 else Lv
             Ad, Bd, Od = A.detach(), B.detach(), Bobs.detach()
-            u = Unrolled([(Od[k].contiguous(), Ad[k].contiguous(), Bd[k].contiguous(), lams[k], Ls[k])
-                          for k in range(N)], iters, ckpt, precision)
+            probs = [(Od[k].contiguous(), Ad[k].contiguous(), Bd[k].contiguous(), lams[k], Ls[k]) for k in range(N)]
+            if plan is None:
+                u = Unrolled(probs, iters, ckpt, precision)
+            else:
+                u = plan
+                u.update(probs)
             X = torch.stack(u.forward())
             ctx.plan = u
+            ctx.owned = plan is None
             ctx.lam_shape = lam.shape
             return X
 
@@ -384,17 +410,23 @@ def _unrolled_function():
         def backward(ctx, dX):
             N = dX.shape[0]
             dA, dB, dl = ctx.plan.backward([dX[k] for k in range(N)])
-            ctx.plan.close()
+            if ctx.owned:
+                ctx.plan.close()
             dlam = torch.tensor(dl, dtype=torch.float64, device=dX.device)
             dlam = dlam.sum().reshape(ctx.lam_shape) if ctx.lam_shape.numel() == 1 else dlam.reshape(ctx.lam_shape)
-            return torch.stack(dA), torch.stack(dB), dlam, None, None, None, None, None
+            return torch.stack(dA), torch.stack(dB), dlam, None, None, None, None, None, None
 
     return SfistaUnrolledFn
 
 
-def unrolled(A, B, lam, Bobs, L=None, iters: int = 50, ckpt: int = 10, precision: str = "fp32"):
+def unrolled(A, B, lam, Bobs, L=None, iters: int = 50, ckpt: int = 10, precision: str = "fp32", plan=None):
     """X = unrolled sFISTA of a batch: A (N, r, n, n), B (N, r, m, m), lam a
     scalar or (N,) tensor, Bobs (N, m, n), all float64 on the GPU; L None
     (power estimate per image), a float, or (N,) values.  Differentiable in
-    A, B and lam with torch.autograd."""
-    return _unrolled_function().apply(A, B, lam, Bobs, L, iters, ckpt, precision)
+    A, B and lam with torch.autograd.  ``plan``: an ``Unrolled`` handle of
+    these sizes to reuse (its iters, ckpt and precision apply; the call
+    updates it, so one backward must run before the next forward); without
+    one, each call sets up and releases a handle of its own."""
+    if plan is not None:
+        iters, ckpt, precision = plan.iters, plan.ckpt, plan.precision
+    return _unrolled_function().apply(A, B, lam, Bobs, L, iters, ckpt, precision, plan)

@@ -165,4 +165,5 @@ def test_diff_calls_reject_null(L):
     assert L.sfista_diff_forward(None, None) == -1
     assert L.sfista_diff_backward(None, P(), P(), P(), d) == -1
     assert L.sfista_diff_get_L(None, d) == -1
+    assert L.sfista_diff_update(None, _items(), 2) == -1
     L.sfista_diff_destroy(None)

@@ -143,3 +143,89 @@ def test_uneven_batch_matches_single_images(sf):
         assert rel(host(X), O.sfista64(K, H, B, lam, L, 13)) < 1e-12
         assert rel(host(a), oK) < 1e-10 and rel(host(b), oH) < 1e-10
         assert abs(l - olam) <= 1e-10 * abs(olam)
+
+
+def test_cached_pool_reuse_and_release(sf):
+    """Handles made after earlier handles died reuse the pool's cached
+    blocks; results are bitwise those of the first handle, also after the
+    cache has been handed back."""
+    K, H, B, x, L = _small(seed=33)
+    first = _gpu_grad(sf, K, H, B, x, 0.1, L, 6, 3, "fp64")
+    again = _gpu_grad(sf, K, H, B, x, 0.1, L, 6, 3, "fp64")
+    sf.release_cached()
+    after = _gpu_grad(sf, K, H, B, x, 0.1, L, 6, 3, "fp64")
+    for a, b, c in zip(first, again, after):
+        assert np.array_equal(np.asarray(a), np.asarray(b))
+        assert np.array_equal(np.asarray(a), np.asarray(c))
+
+
+def test_update_matches_fresh_setup(sf):
+    """A handle updated with new problems (factors, observations, lambda, L
+    re-estimated) gives bitwise the results of a handle set up on them, and
+    those match the oracle; updates of other sizes or counts are refused."""
+    a = [_small(m=40, n=56, r=2, seed=41), _small(m=64, n=48, r=2, seed=42)]
+    b = [_small(m=40, n=56, r=2, seed=43), _small(m=64, n=48, r=2, seed=44)]
+    lam_a, lam_b = [0.1, 0.15], [0.2, 0.05]
+
+    def probs(cases, lams, est):
+        return [(dev(B), dev(K), dev(H), lam, None if est else L) for (K, H, B, x, L), lam in zip(cases, lams)]
+
+    def run(u, cases):
+        Xs = u.forward()
+        dXs = [2.0 * (X - dev(c[3])) / X.numel() for X, c in zip(Xs, cases)]
+        dA, dB, dl = u.backward(dXs)
+        return [host(X) for X in Xs], [host(t) for t in dA], [host(t) for t in dB], dl
+
+    u = sf.Unrolled(probs(a, lam_a, False), iters=9, ckpt=4, precision="fp64")
+    run(u, a)
+    u.update(probs(b, lam_b, True))
+    got = run(u, b)
+    L_upd = u.L
+    with pytest.raises(ValueError):
+        u.update(probs([a[1], a[0]], lam_a, False))
+    # the library's own checks: count, then sizes
+    items, _, _, _ = sf.Unrolled._items(probs(b[:1], lam_b[:1], False))
+    assert sf.lib().sfista_diff_update(u._h, items, 1) == -1
+    items, _, _, _ = sf.Unrolled._items(probs([a[1], a[0]], lam_a, False))
+    assert sf.lib().sfista_diff_update(u._h, items, 2) == -1
+    assert u.L == L_upd
+    u.close()
+    f = sf.Unrolled(probs(b, lam_b, True), iters=9, ckpt=4, precision="fp64")
+    ref = run(f, b)
+    L_ref = f.L
+    f.close()
+    assert L_upd == L_ref
+    for g, r_ in zip(got[:3], ref[:3]):
+        for x, y in zip(g, r_):
+            assert np.array_equal(x, y)
+    assert got[3] == ref[3]
+    for (K, H, B, x, _), lam, L, X, dA, dB, dl in zip(b, lam_b, L_ref, *got):
+        loss, oK, oH, olam = O.sfista64_grad(K, H, B, lam, L, 9, x)
+        assert rel(X, O.sfista64(K, H, B, lam, L, 9)) < 1e-12
+        assert rel(dA, oK) < 1e-10 and rel(dB, oH) < 1e-10
+        assert abs(dl - olam) <= 1e-10 * abs(olam)
+
+
+def test_autograd_reuses_plan(sf):
+    """The autograd wrapper with a reused handle: two training steps with
+    different factors give the gradients of fresh handles."""
+    import torch
+    cases = [_small(m=48, n=48, r=2, seed=51), _small(m=48, n=48, r=2, seed=52)]
+    Bobs = torch.stack([dev(c[2]) for c in cases])
+    xt = torch.stack([dev(c[3]) for c in cases])
+    Ls = [c[4] for c in cases]
+    plan = sf.Unrolled([(dev(c[2]), dev(c[0]), dev(c[1]), 0.1, c[4]) for c in cases], iters=7, ckpt=3,
+                       precision="fp64")
+    for step, scale in enumerate((1.0, 0.9)):
+        grads = []
+        for pl in (plan, None):
+            A = torch.stack([dev(c[0]) * scale for c in cases]).requires_grad_(True)
+            B = torch.stack([dev(c[1]) for c in cases]).requires_grad_(True)
+            lam = torch.tensor(0.1 + 0.01 * step, dtype=torch.float64, device="cuda:0", requires_grad=True)
+            X = sf.unrolled(A, B, lam, Bobs, L=Ls, iters=7, ckpt=3, precision="fp64", plan=pl)
+            ((X - xt) ** 2).sum().backward()
+            grads.append((host(A.grad), host(B.grad), lam.grad.item()))
+        assert np.array_equal(grads[0][0], grads[1][0])
+        assert np.array_equal(grads[0][1], grads[1][1])
+        assert grads[0][2] == grads[1][2]
+    plan.close()
