@@ -85,18 +85,44 @@ static __global__ void diff_out_kernel(const DiffImg* im, int t) {
     d.xout[e] = d.xs[(long)t * mn + e];
 }
 
+// The transposing kernels give each thread one column j and a strip of CE
+// consecutive rows i (CE = 16 / element size): its reads are coalesced
+// across threads along j, and its CE values make one whole 16-byte chunk of
+// the transposed operand row j.
+template <int MODE>
+__device__ __forceinline__ void store_chunk_t(void* const* g, long ld, long row, long k0, const double* v, int cnt) {
+  constexpr int CE = 16 / ModeTraits<MODE>::esize;
+  if (cnt == CE && k0 % CE == 0) {
+    const long idx = op_index<MODE>(row, k0, ld);
+    if constexpr (MODE == M_F64) {
+      *reinterpret_cast<double2*>(static_cast<double*>(g[0]) + idx) = make_double2(v[0], v[1]);
+    } else {
+      static_assert(MODE == M_F32, "the differentiable form runs in FP32 or FP64");
+      *reinterpret_cast<float4*>(static_cast<float*>(g[0]) + idx) =
+          make_float4((float)v[0], (float)v[1], (float)v[2], (float)v[3]);
+    }
+  } else {
+    for (int q = 0; q < cnt; ++q) store_planes<MODE>(g, op_index<MODE>(row, k0 + q, ld), v[q]);
+  }
+}
+
 // Y_k^T (ys slot t - 1) into the gradient operand AB at iteration slot
 // `slot` (K offset slot * m).
 template <int MODE>
 __global__ void diff_pack_y_kernel(const DiffImg* im, int t, int slot) {
+  constexpr int CE = 16 / ModeTraits<MODE>::esize;
   const DiffImg d = im[blockIdx.y];
   const long koff = (long)slot * d.m;
   const long mn = (long)d.m * d.n;
   const double* y = d.ys + (long)(t - 1) * mn;
   void* g[2] = {d.AB[0], d.AB[1]};
-  for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < mn; e += (long)gridDim.x * blockDim.x) {
-    const long i = e / d.n, j = e - i * d.n;
-    store_planes<MODE>(g, op_index<MODE>(j, koff + i, d.ldAB), y[e]);
+  const long strips = (d.m + CE - 1) / CE;
+  for (long u = blockIdx.x * (long)blockDim.x + threadIdx.x; u < strips * d.n; u += (long)gridDim.x * blockDim.x) {
+    const long sidx = u / d.n, j = u - sidx * d.n, i0 = sidx * CE;
+    const int cnt = (int)(d.m - i0 < CE ? d.m - i0 : CE);
+    double v[CE];
+    for (int q = 0; q < CE; ++q) v[q] = q < cnt ? y[(i0 + q) * d.n + j] : 0.0;
+    store_chunk_t<MODE>(g, d.ldAB, j, koff + i0, v, cnt);
   }
 }
 
@@ -107,21 +133,33 @@ __global__ void diff_pack_y_kernel(const DiffImg* im, int t, int slot) {
 // `slot` (K offset slot * m).
 template <int MODE>
 __global__ void diff_adjoint_kernel(const DiffImg* im, int k, int last, double a1, double a2, int slot) {
+  constexpr int CE = 16 / ModeTraits<MODE>::esize;
   const DiffImg d = im[blockIdx.y];
   const long koff = (long)slot * d.m;
-  const long mn = (long)d.m * d.n;
-  const double* yb1 = d.yb[(k + 1) % 3];
-  const double* yb2 = d.yb[(k + 2) % 3];
+  // the rotating buffers are picked in global memory: a run-time index into
+  // the private copy would move that copy to scratch
+  const double* yb1 = im[blockIdx.y].yb[(k + 1) % 3];
+  const double* yb2 = im[blockIdx.y].yb[(k + 2) % 3];
   void* p[2] = {d.Xop[0], d.Xop[1]};
   void* g[2] = {d.AB[0], d.AB[1]};
-  for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < mn; e += (long)gridDim.x * blockDim.x) {
-    double xb = a1 * yb1[e] - a2 * yb2[e];
-    if (last) xb += d.dX[e];
-    d.xbar[e] = xb;
-    const double gb = -d.c2 * xb;
-    const long i = e / d.n, j = e - i * d.n;
-    store_planes<MODE>(p, op_index<MODE>(i, j, d.ldY), gb);
-    store_planes<MODE>(g, op_index<MODE>(j, koff + i, d.ldAB), gb);
+  const long strips = (d.m + CE - 1) / CE;
+  for (long u = blockIdx.x * (long)blockDim.x + threadIdx.x; u < strips * d.n; u += (long)gridDim.x * blockDim.x) {
+    const long sidx = u / d.n, j = u - sidx * d.n, i0 = sidx * CE;
+    const int cnt = (int)(d.m - i0 < CE ? d.m - i0 : CE);
+    double v[CE];
+    for (int q = 0; q < CE; ++q) {
+      v[q] = 0.0;
+      if (q < cnt) {
+        const long e = (i0 + q) * d.n + j;
+        double xb = a1 * yb1[e] - a2 * yb2[e];
+        if (last) xb += d.dX[e];
+        d.xbar[e] = xb;
+        const double gb = -d.c2 * xb;
+        store_planes<MODE>(p, op_index<MODE>(i0 + q, j, d.ldY), gb);
+        v[q] = gb;
+      }
+    }
+    store_chunk_t<MODE>(g, d.ldAB, j, koff + i0, v, cnt);
   }
 }
 
@@ -153,8 +191,8 @@ static __global__ void diff_clear_kernel(const DiffImg* im, int K, int r) {
   const DiffImg d = im[blockIdx.y];
   const long mn = (long)d.m * d.n;
   const long na = (long)r * d.n * d.n, nb = (long)r * d.m * d.m;
-  double* y1 = d.yb[(K + 1) % 3];
-  double* y2 = d.yb[(K + 2) % 3];
+  double* y1 = im[blockIdx.y].yb[(K + 1) % 3];
+  double* y2 = im[blockIdx.y].yb[(K + 2) % 3];
   for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < std::max(mn, std::max(na, nb));
        e += (long)gridDim.x * blockDim.x) {
     if (e < mn) { y1[e] = 0.0; y2[e] = 0.0; }
