@@ -108,6 +108,15 @@ typedef struct sfista_plan* sfista_handle;
 int kron_approx(const double* P, int m, int n, int l, int q, int bc, int r,
                 double* A, double* B, double* sigma, double* eps_s, hipStream_t stream);
 
+/* The same approximation, returned as its generator vectors instead of dense
+ * factors (Section 2): h (device, out) r x m and k (device, out) r x n, FP64,
+ * with B_k = toep(h_k, l + 1) [+ hank(h_k, l + 1)] and A_k = toep(k_k, q + 1)
+ * [+ hank(k_k, q + 1)] in the paper's 1-based notation (Hankel part for the
+ * reflexive boundary), so that kron_approx's factors are their expansions.  Arguments, checks, sigma and
+ * eps_s as in kron_approx. */
+int kron_generators(const double* P, int m, int n, int l, int q, int bc, int r,
+                    double* h, double* k, double* sigma, double* eps_s, hipStream_t stream);
+
 /* Build a solver plan for Algorithm 2 (sFISTA).
  *   Bobs   (device) m x n FP64 observed image.
  *   A, B   (device) dense factors as produced by kron_approx (any real factors
@@ -256,6 +265,36 @@ int sfista_diff_backward(sfista_diff_handle h, const double* const* dX, double* 
 int sfista_diff_get_L(sfista_diff_handle h, double* L);
 
 void sfista_diff_destroy(sfista_diff_handle h);
+
+/* ---------------------------------------------------------------------
+ * Structured-FFT form (Section 3.3): the iteration of Algorithm 2 with each
+ * Kronecker factor applied through its generator by 1-D FFTs instead of as
+ * a dense matrix.  A factor toep(c, j) [+ hank(c, j)] times a line is a
+ * convolution of the boundary-extended line with c; its transpose is the
+ * matching correlation with the extension folded back.  Two real lines share
+ * one complex transform.  Transforms are FP32 (radix-16 Stockham in LDS),
+ * iterates FP64; a transform covers 2M - 1 points, so m, n <= 4096.
+ *
+ *   Bobs   (device) m x n FP64 observed image.
+ *   h, k   (device) r x m and r x n FP64 generators as made by
+ *          kron_generators (any real generators are accepted).
+ *   l, q   0-based centre (the PSF's), bc the boundary.
+ *   p      (host) lambda, L (<= 0: power estimate), nonneg, power_iters, x0,
+ *          v0 as for sfista_setup; precision and pair_state are ignored.
+ * Setup copies what it needs and synchronises `stream`; later calls run on
+ * it.  sfista_fft_step is asynchronous; sfista_fft_solve and sfista_fft_apply
+ * (A_s X and A_s^T A_s X, each output nullable) return after their work.
+ * The report's residual uses Bobs rounded to FP32, as the iteration does.
+ * --------------------------------------------------------------------- */
+typedef struct sfista_fft* sfista_fft_handle;
+
+int sfista_fft_setup(const double* Bobs, int m, int n, const double* h, const double* k, int r, int l, int q,
+                     int bc, const sfista_params* p, hipStream_t stream, sfista_fft_handle* out);
+int sfista_fft_step(sfista_fft_handle h, int iters);
+int sfista_fft_solve(sfista_fft_handle h, int max_iters, double tol, double* X_out, sfista_report* rep);
+int sfista_fft_apply(sfista_fft_handle h, const double* X, double* AX, double* AtAX);
+int sfista_fft_get_L(sfista_fft_handle h, double* L);
+void sfista_fft_destroy(sfista_fft_handle h);
 
 /* Lipschitz constant in use by the plan (estimated or given). */
 int sfista_get_L(sfista_handle h, double* L);

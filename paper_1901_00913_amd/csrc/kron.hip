@@ -416,12 +416,10 @@ struct TailSq {        // P_bar[a][b] - sum_k sigma_k u_k[a] v_k[b]
   }
 };
 
-}  // namespace
-
-extern "C" int kron_approx(const double* P, int m, int n, int l, int q, int bc, int r, double* A, double* B,
-                           double* sigma, double* eps_s, hipStream_t s) {
-  clear_error();
-  if (!P || !A || !B) return set_error(SFISTA_ERR_ARG, "NULL device pointer");
+// The common body of kron_approx and kron_generators: dense factors (A, B)
+// and generators (h, k) are each optional.
+int kron_impl(const double* P, int m, int n, int l, int q, int bc, int r, double* A, double* B, double* h_out,
+              double* k_out, double* sigma, double* eps_s, hipStream_t s) {
   if (m < 1 || n < 1) return set_error(SFISTA_ERR_ARG, "PSF size %d x %d must be positive", m, n);
   if (l < 0 || l >= m || q < 0 || q >= n) return set_error(SFISTA_ERR_ARG, "centre (%d, %d) outside the PSF", l, q);
   if (bc != SFISTA_BC_ZERO && bc != SFISTA_BC_REFLEXIVE) return set_error(SFISTA_ERR_ARG, "unknown boundary %d", bc);
@@ -477,9 +475,11 @@ extern "C" int kron_approx(const double* P, int m, int n, int l, int q, int bc, 
   hipLaunchKernelGGL(finish_vectors_kernel, dim3(16, r), dim3(256), 0, s, Yc, Zc, Wm, sig, order, p, r, m, n, U, V,
                      sig_out);
   hipLaunchKernelGGL(generators_kernel, dim3(r), dim3(ST), 0, s, U, V, sig_out, m, n, l, q, bc, rm, rn, gh, gk);
-  hipLaunchKernelGGL(expand_kernel, ew, et, 0, s, gh, r, m, l, bc, B);
-  hipLaunchKernelGGL(expand_kernel, ew, et, 0, s, gk, r, n, q, bc, A);
+  if (B) hipLaunchKernelGGL(expand_kernel, ew, et, 0, s, gh, r, m, l, bc, B);
+  if (A) hipLaunchKernelGGL(expand_kernel, ew, et, 0, s, gk, r, n, q, bc, A);
   hipError_t e = hipGetLastError();
+  if (e == hipSuccess && h_out) e = hipMemcpyAsync(h_out, gh, (size_t)r * m * 8, hipMemcpyDeviceToDevice, s);
+  if (e == hipSuccess && k_out) e = hipMemcpyAsync(k_out, gk, (size_t)r * n * 8, hipMemcpyDeviceToDevice, s);
   if (e != hipSuccess) return hip_fail(e, "kron_approx launch");
   if ((e = sumsq(TailSq{Pb, U, V, sig_out, r, m, n}, mn, red, red + RED_BLOCKS, s)) != hipSuccess)
     return hip_fail(e, "kron_approx tail norm");
@@ -493,4 +493,20 @@ extern "C" int kron_approx(const double* P, int m, int n, int l, int q, int bc, 
   if (eps_s) *eps_s = sqrt(tail);
   if (!isfinite(tail)) return set_error(SFISTA_ERR_NONFINITE, "non-finite approximation error");
   return SFISTA_OK;
+}
+
+}  // namespace
+
+extern "C" int kron_approx(const double* P, int m, int n, int l, int q, int bc, int r, double* A, double* B,
+                           double* sigma, double* eps_s, hipStream_t s) {
+  clear_error();
+  if (!P || !A || !B) return set_error(SFISTA_ERR_ARG, "NULL device pointer");
+  return kron_impl(P, m, n, l, q, bc, r, A, B, nullptr, nullptr, sigma, eps_s, s);
+}
+
+extern "C" int kron_generators(const double* P, int m, int n, int l, int q, int bc, int r, double* h, double* k,
+                               double* sigma, double* eps_s, hipStream_t s) {
+  clear_error();
+  if (!P || !h || !k) return set_error(SFISTA_ERR_ARG, "NULL device pointer");
+  return kron_impl(P, m, n, l, q, bc, r, nullptr, nullptr, h, k, sigma, eps_s, s);
 }

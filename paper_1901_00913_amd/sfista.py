@@ -34,7 +34,9 @@ EXPORTS = ("kron_approx", "sfista_setup", "sfista_step", "sfista_solve", "sfista
            "sfista_set_timing", "sfista_kernel_times", "sfista_get_L", "sfista_destroy",
            "sfista_last_error", "sfista_batch_setup", "sfista_batch_solve", "sfista_batch_tiles",
            "sfista_batch_destroy", "sfista_diff_setup", "sfista_diff_forward", "sfista_diff_backward",
-           "sfista_diff_get_L", "sfista_diff_destroy", "sfista_diff_update", "sfista_release_cached")
+           "sfista_diff_get_L", "sfista_diff_destroy", "sfista_diff_update", "sfista_release_cached",
+           "kron_generators", "sfista_fft_setup", "sfista_fft_step", "sfista_fft_solve", "sfista_fft_apply",
+           "sfista_fft_get_L", "sfista_fft_destroy")
 
 BATCH_AUTOTUNE = 1
 BATCH_GRAPH = 2
@@ -104,12 +106,21 @@ def lib() -> ctypes.CDLL:
     L.sfista_diff_destroy.argtypes = [vp]
     L.sfista_diff_destroy.restype = None
     L.sfista_release_cached.argtypes = []
+    L.kron_generators.argtypes = [vp, i, i, i, i, i, i, vp, vp, vp, vp, vp]
+    L.sfista_fft_setup.argtypes = [vp, i, i, vp, vp, i, i, i, i, ctypes.POINTER(Params), vp, ctypes.POINTER(vp)]
+    L.sfista_fft_step.argtypes = [vp, i]
+    L.sfista_fft_solve.argtypes = [vp, i, d, vp, ctypes.POINTER(Report)]
+    L.sfista_fft_apply.argtypes = [vp, vp, vp, vp]
+    L.sfista_fft_get_L.argtypes = [vp, ctypes.POINTER(d)]
+    L.sfista_fft_destroy.argtypes = [vp]
+    L.sfista_fft_destroy.restype = None
     L.sfista_last_error.argtypes = []
     L.sfista_last_error.restype = ctypes.c_char_p
     for name in ("kron_approx", "sfista_setup", "sfista_step", "sfista_solve", "sfista_apply", "sfista_get_L",
                  "sfista_set_timing", "sfista_kernel_times", "sfista_batch_setup", "sfista_batch_solve",
                  "sfista_batch_tiles", "sfista_diff_setup", "sfista_diff_forward", "sfista_diff_backward",
-                 "sfista_diff_get_L", "sfista_diff_update", "sfista_release_cached"):
+                 "sfista_diff_get_L", "sfista_diff_update", "sfista_release_cached", "kron_generators",
+                 "sfista_fft_setup", "sfista_fft_step", "sfista_fft_solve", "sfista_fft_apply", "sfista_fft_get_L"):
         getattr(L, name).restype = ctypes.c_int
     _lib = L
     return L
@@ -153,6 +164,83 @@ def kron_approx(P, l: int, q: int, bc: int, r: int, stream=None):
                              ctypes.cast(sig, ctypes.c_void_p), ctypes.cast(ctypes.byref(eps), ctypes.c_void_p),
                              _stream(stream)))
     return A, B, np.array(sig[:r]), eps.value
+
+
+def kron_generators(P, l: int, q: int, bc: int, r: int, stream=None):
+    """The approximation of :func:`kron_approx` as generator vectors:
+    ``(h, k, sigma, eps_s)`` with ``h`` (r, m) and ``k`` (r, n) device tensors;
+    ``B_k`` and ``A_k`` are their Toeplitz (+ Hankel) expansions."""
+    import torch
+    m, n = P.shape
+    h = torch.empty((r, m), dtype=torch.float64, device=P.device)
+    k = torch.empty((r, n), dtype=torch.float64, device=P.device)
+    sig = (ctypes.c_double * max(r, 1))()
+    eps = ctypes.c_double(0.0)
+    _check(lib().kron_generators(_dev_f64(P, "P"), m, n, l, q, bc, r, h.data_ptr(), k.data_ptr(),
+                                 ctypes.cast(sig, ctypes.c_void_p), ctypes.cast(ctypes.byref(eps), ctypes.c_void_p),
+                                 _stream(stream)))
+    return h, k, np.array(sig[:r]), eps.value
+
+
+class FftSolver:
+    """Structured-FFT sFISTA plan for one image: the factors enter through
+    their generators ``h`` (r, m) and ``k`` (r, n), centre ``(l, q)`` and
+    boundary ``bc``, and are applied by 1-D FFTs (FP32 transforms, FP64
+    iterates)."""
+
+    def __init__(self, Bobs, h, k, l: int, q: int, bc: int, lam: float, L: Optional[float] = None,
+                 nonneg: bool = False, power_iters: int = 0, x0=None, v0=None, stream=None):
+        m, n = Bobs.shape
+        r = h.shape[0]
+        if h.shape != (r, m) or k.shape != (r, n):
+            raise ValueError("h must be (r, m) and k (r, n) for Bobs of shape (m, n)")
+        p = Params(float(lam), float(L) if L is not None else 0.0, PRECISIONS["fp32"], int(bool(nonneg)),
+                   int(power_iters), 0, _dev_f64(x0, "x0") if x0 is not None else None,
+                   _dev_f64(v0, "v0") if v0 is not None else None)
+        hd = ctypes.c_void_p()
+        self._h = None
+        self.shape = (m, n)
+        self.device = Bobs.device
+        _check(lib().sfista_fft_setup(_dev_f64(Bobs, "Bobs"), m, n, _dev_f64(h, "h"), _dev_f64(k, "k"), r, int(l),
+                                      int(q), int(bc), ctypes.byref(p), _stream(stream), ctypes.byref(hd)))
+        self._h = hd
+
+    @property
+    def L(self) -> float:
+        v = ctypes.c_double()
+        _check(lib().sfista_fft_get_L(self._h, ctypes.byref(v)))
+        return v.value
+
+    def step(self, iters: int):
+        _check(lib().sfista_fft_step(self._h, int(iters)))
+
+    def solve(self, max_iters: int, tol: float = 0.0, want_x: bool = True):
+        import torch
+        X = torch.empty(self.shape, dtype=torch.float64, device=self.device) if want_x else None
+        rep = Report()
+        _check(lib().sfista_fft_solve(self._h, int(max_iters), float(tol), X.data_ptr() if want_x else None,
+                                      ctypes.byref(rep)))
+        return X, rep.as_dict()
+
+    def apply(self, X, want_ax: bool = True, want_atax: bool = True):
+        """``(sum_k B_k X A_k^T, A_s^T A_s X)`` by the plan's transforms."""
+        import torch
+        ax = torch.empty(self.shape, dtype=torch.float64, device=self.device) if want_ax else None
+        atax = torch.empty(self.shape, dtype=torch.float64, device=self.device) if want_atax else None
+        _check(lib().sfista_fft_apply(self._h, _dev_f64(X, "X"), ax.data_ptr() if want_ax else None,
+                                      atax.data_ptr() if want_atax else None))
+        return ax, atax
+
+    def close(self):
+        if self._h is not None:
+            lib().sfista_fft_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 class Solver:

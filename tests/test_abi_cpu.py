@@ -167,3 +167,35 @@ def test_diff_calls_reject_null(L):
     assert L.sfista_diff_get_L(None, d) == -1
     assert L.sfista_diff_update(None, _items(), 2) == -1
     L.sfista_diff_destroy(None)
+
+
+@pytest.mark.parametrize("args,expect", [
+    (dict(m=0), -1), (dict(n=5000), -2), (dict(r=0), -1), (dict(r=5, m=4, n=4), -1),
+    (dict(r=65, m=100, n=100), -2), (dict(l=4), -1), (dict(q=-1), -1), (dict(bc=2), -1),
+    (dict(lambda_=-1.0), -1), (dict(L=float("nan")), -1), (dict(power_iters=-1), -1),
+])
+def test_fft_setup_rejects_invalid_arguments(L, args, expect):
+    m, n, r = args.pop("m", 4), args.pop("n", 4), args.pop("r", 1)
+    l, q, bc = args.pop("l", 1), args.pop("q", 1), args.pop("bc", 1)
+    p = _params(**args)
+    h = ctypes.c_void_p()
+    rc = L.sfista_fft_setup(FAKE, m, n, FAKE, FAKE, r, l, q, bc, ctypes.byref(p), None, ctypes.byref(h))
+    assert rc == expect
+    assert h.value is None
+    assert L.sfista_last_error()
+
+
+def test_fft_calls_reject_null(L):
+    h = ctypes.c_void_p()
+    p = _params()
+    assert L.sfista_fft_setup(None, 4, 4, FAKE, FAKE, 1, 1, 1, 0, ctypes.byref(p), None, ctypes.byref(h)) == -1
+    assert L.sfista_fft_setup(FAKE, 4, 4, None, FAKE, 1, 1, 1, 0, ctypes.byref(p), None, ctypes.byref(h)) == -1
+    assert L.sfista_fft_setup(FAKE, 4, 4, FAKE, FAKE, 1, 1, 1, 0, None, None, ctypes.byref(h)) == -1
+    assert L.sfista_fft_setup(FAKE, 4, 4, FAKE, FAKE, 1, 1, 1, 0, ctypes.byref(p), None, None) == -1
+    assert L.sfista_fft_step(None, 1) == -1
+    assert L.sfista_fft_solve(None, 1, 0.0, None, None) == -1
+    assert L.sfista_fft_apply(None, FAKE, None, None) == -1
+    assert L.sfista_fft_get_L(None, ctypes.byref(ctypes.c_double())) == -1
+    L.sfista_fft_destroy(None)
+    assert L.kron_generators(FAKE, 4, 4, 1, 1, 0, 1, None, FAKE, None, None, None) == -1
+    assert L.kron_generators(FAKE, 4, 4, 4, 1, 0, 1, FAKE, FAKE, None, None, None) == -1
