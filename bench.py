@@ -15,6 +15,7 @@ Prints one JSON line on stdout; progress goes to stderr.
 
 import argparse
 import json
+import math
 import os
 import sys
 import time
@@ -263,6 +264,74 @@ def run_paper(args, dev, steps, warmup):
     return {"line": line, "summary": rows}
 
 
+def run_fft(args, dev, steps, warmup):
+    """Structured-FFT form on the precision workload (2048^2, r = 5,
+    reflexive, 300 iterations): a step runs kron_generators, the plan setup
+    with the power estimate of L and the iterations, as the default line does
+    with dense factors.  Transforms are FP32, iterates FP64."""
+    import torch
+
+    import synth as S
+    from paper_1901_00913_amd import sfista
+
+    p = S.config(3, n=args.n, iters=args.iters)
+    m, n = p.shape
+    l, q = p.center
+    r, iters = p.r, p.iters
+    P = torch.as_tensor(p.psf).to(dev)
+    Bobs = torch.as_tensor(p.bobs).to(dev)
+    v0 = torch.as_tensor(p.v0).to(dev)
+
+    def step():
+        h, k, _, eps = sfista.kron_generators(P, l, q, p.bc, r)
+        s = sfista.FftSolver(Bobs, h, k, l, q, p.bc, lam=p.lam, power_iters=args.power_iters, v0=v0)
+        _, rep = s.solve(iters, want_x=False)
+        L = s.L
+        s.close()
+        return rep, L
+
+    for w in range(warmup):
+        log(f"[fft] warmup step {w + 1}/{warmup}")
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    reps = [step() for _ in range(steps)]
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    value = iters * steps / elapsed
+    iter_s = sum(rp["seconds"] for rp, _ in reps) / steps
+    # transforms per iteration: four line passes, each r + 1 transforms per
+    # pair of lines; 5 N log2 N flops per complex transform of N points
+    def nfft(M):
+        N = 64
+        while N < 2 * M - 1:
+            N *= 2
+        return N
+    Nm, Nn = nfft(m), nfft(n)
+    fl = lambda N, lines: (r + 1) * ((lines + 1) // 2) * 5.0 * N * math.log2(N)
+    flops_it = 2 * fl(Nn, m) + 2 * fl(Nm, n)
+    bytes_it = m * n * (52 + 16 * r)   # algorithmic HBM bytes of the four passes
+    log(f"[fft] {steps} steps in {elapsed:.3f} s -> {value:.1f} it/s; iterations only {iters / iter_s:.1f} it/s")
+    summary = {"its_per_s": value, "iteration_only_its": iters / iter_s, "ms_per_step": elapsed / steps * 1e3,
+               "fft_tflops": flops_it / (iter_s / iters) / 1e12,
+               "fft_frac_of_fp32_vector_peak": flops_it / (iter_s / iters) / 1e12 / PEAK_TFLOPS["fp32"],
+               "hbm_tb_per_s": bytes_it / (iter_s / iters) / 1e12, "transform_sizes": [Nm, Nn],
+               "L": reps[-1][1], "resid_rel": reps[-1][0]["resid_rel"], "phi_s": reps[-1][0]["phi_s"]}
+    line = {
+        "metric": "sFISTA iterations/s, structured-FFT form, 2048^2, r=5", "value": value, "unit": "iters/s",
+        "n_gpus": 1, "steps": steps, "warmup": warmup, "ms_per_step": elapsed / steps * 1e3,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "fp32", "data": "synthetic",
+        "config": {"workload": f"sfista-fft-{m}x{n}-r{r}-reflexive-{iters}it", "image": [m, n], "rank": r,
+                   "iters": iters, "parallelism": "single-gpu"},
+        "roofline": {"bound": "alu", "kernel": "fan_in_kernel / fan_out_kernel (all four line passes)",
+                     "achieved": summary["fft_tflops"], "peak": PEAK_TFLOPS["fp32"], "unit": "TFLOP/s",
+                     "frac": summary["fft_frac_of_fp32_vector_peak"], "traffic": None},
+        "cpu_baseline": None,
+        "extra": summary,
+    }
+    return {"line": line, "summary": summary}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -276,13 +345,15 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp32-compare", action="store_true")
     ap.add_argument("--workload", default="precision-2048",
-                    choices=("precision-2048", "batch64", "diff8", "paper256"),
+                    choices=("precision-2048", "batch64", "diff8", "paper256", "fft2048"),
                     help="precision-2048: one 2048^2 image, r = 5 (default); batch64: 64 uneven images "
                          "in grouped launches replayed from a HIP graph; diff8: gradient of 50 unrolled "
                          "iterations for 8 images at 512^2, r = 4; paper256: the paper-shaped sweep "
-                         "(256^2, reflexive, 1% noise, defocus and motion blur, s = 1..5, 50 iterations)")
+                         "(256^2, reflexive, 1% noise, defocus and motion blur, s = 1..5, 50 iterations); "
+                         "fft2048: the default workload in the structured-FFT form")
     ap.add_argument("--no-batch", action="store_true", help="skip the batch64 summary in the default line")
     ap.add_argument("--no-diff", action="store_true", help="skip the diff8 summary in the default line")
+    ap.add_argument("--no-fft", action="store_true", help="skip the fft2048 summary in the default line")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="after the timed steps, copy a BYTES-long device buffer once (a plain copy kernel "
                          "of known traffic, for scaling hardware byte counters)")
@@ -305,8 +376,8 @@ def main():
     sfista.lib()
     dev = torch.device("cuda:0")
 
-    if args.workload in ("batch64", "diff8", "paper256"):
-        res = {"batch64": run_batch, "diff8": run_diff, "paper256": run_paper}[args.workload](
+    if args.workload in ("batch64", "diff8", "paper256", "fft2048"):
+        res = {"batch64": run_batch, "diff8": run_diff, "paper256": run_paper, "fft2048": run_fft}[args.workload](
             args, dev, args.steps, args.warmup)
         print(json.dumps(res["line"]), flush=True)
         return
@@ -434,6 +505,10 @@ def main():
         extra["batch64"] = run_batch(args, dev, 1, 1)["summary"]
     if not args.no_diff:
         extra["diff8"] = run_diff(args, dev, 1, 1)["summary"]
+    if not args.no_fft:
+        fsum = run_fft(args, dev, 1, 1)["summary"]
+        fsum["iteration_speedup_vs_gemm_form"] = fsum["iteration_only_its"] / iter_rate
+        extra["fft2048"] = fsum
 
     out = {
         "metric": METRIC, "value": value, "unit": "iters/s", "n_gpus": 1, "steps": args.steps,
