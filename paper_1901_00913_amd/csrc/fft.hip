@@ -18,7 +18,11 @@
 // the inverse transform keep them apart.  The transform is a mixed-radix
 // Stockham FFT (radix 16, then 2, 4 or 8) held in LDS: each pass reads its
 // butterflies' inputs into registers, synchronises, and writes the outputs in
-// place.  Transforms are FP32; the iterates are FP64.
+// place.  At 4096 points (256 threads) each thread's first-pass inputs and
+// last-pass outputs are the points it loads and stores itself, so those two
+// passes run from and to registers and a transform takes two LDS exchanges.
+// Twiddles come from a table, three reads per pass, the other powers by
+// products.  Transforms are FP32; the iterates are FP64.
 //
 // One iteration is four line passes over the image (m x n, row-major):
 //   F1  T_k = Y A_k^T      rows of Y, one transform in, r out (stored T_k^T)
@@ -155,56 +159,127 @@ __device__ __forceinline__ void dft<16>(float2 (&v)[16]) {   // N1 = N2 = 4
   for (int k = 0; k < 16; ++k) v[k] = o[k];
 }
 
-// One Stockham pass of radix R over sub-transforms of size NS already done:
-// butterfly j reads buf[j + r N/R] (twiddled by W_N^((j mod NS) r N/(NS R))),
-// and writes buf[(j / NS) NS R + j mod NS + r NS].  `tw` holds W_N^t.
-template <int N, int NS, int R>
-__device__ __forceinline__ void stockham_pass(float2* buf, const float2* __restrict__ tw) {
-  constexpr int FT = fft_threads(N);
-  constexpr int NB = N / R;
-  constexpr int U = (NB + FT - 1) / FT;
-  float2 v[U][R];
-#pragma unroll
-  for (int u = 0; u < U; ++u) {
-    const int j = (int)threadIdx.x + u * FT;
-    if (NB % FT == 0 || j < NB) {
-#pragma unroll
-      for (int r = 0; r < R; ++r) v[u][r] = buf[j + r * NB];
-      if constexpr (NS > 1) {
-        const int jm = j % NS;
-#pragma unroll
-        for (int r = 1; r < R; ++r) v[u][r] = cmul(v[u][r], tw[jm * r * (N / (NS * R))]);
-      }
-      dft<R>(v[u]);
-    }
+// w[r] = W_N^(t r) for r < R from three table reads (W^t, W^4t, W^8t) and
+// products: each power is at most three roundings away from the table, while
+// the pass needs no more than three loads instead of R - 1.
+template <int R>
+__device__ __forceinline__ void twiddle_powers(float2 (&w)[R], const float2* __restrict__ tw, int t) {
+  w[0] = make_float2(1.f, 0.f);
+  w[1] = tw[t];
+  if constexpr (R >= 4) {
+    w[2] = cmul(w[1], w[1]);
+    w[3] = cmul(w[2], w[1]);
+  } else {
+    return;
   }
-  __syncthreads();
-#pragma unroll
-  for (int u = 0; u < U; ++u) {
-    const int j = (int)threadIdx.x + u * FT;
-    if (NB % FT == 0 || j < NB) {
-      const int d = (j / NS) * NS * R + j % NS;
-#pragma unroll
-      for (int r = 0; r < R; ++r) buf[d + r * NS] = v[u][r];
-    }
+  if constexpr (R >= 8) {
+    w[4] = tw[4 * t];
+    w[5] = cmul(w[4], w[1]);
+    w[6] = cmul(w[4], w[2]);
+    w[7] = cmul(w[4], w[3]);
   }
-  __syncthreads();
+  if constexpr (R >= 16) {
+    w[8] = tw[8 * t];
+#pragma unroll
+    for (int r = 9; r < 16; ++r) w[r] = cmul(w[8], w[r - 8]);
+  }
 }
 
-template <int N, int NS>
-__device__ __forceinline__ void fft_passes(float2* buf, const float2* __restrict__ tw) {
+// Stockham passes, radix 16 first, then 2, 4 or 8; pass (NS, R) works on
+// sub-transforms of size NS already done: butterfly j reads points
+// j + r N/R (twiddled by W_N^((j mod NS) r N/(NS R))) and writes points
+// (j / NS) NS R + j mod NS + r NS.  Thread t takes butterflies t + u FT.
+// A transform may start from registers and end in registers: thread t then
+// holds points t + v FT (x[v], v < N / FT).  The first pass reads exactly
+// those points (butterfly t + u FT, input r is point t + (u + r U) FT with
+// U = N / (R FT)), and the last pass writes them, whenever N / R is a
+// multiple of FT; otherwise the points go through LDS.
+template <int N, int R>
+constexpr bool regs_ok() { return (N / R) % fft_threads(N) == 0; }
+
+constexpr int last_radix(int N) {
+  int ns = 1;
+  while (N / ns > 16) ns *= 16;
+  return N / ns;
+}
+
+template <int N, int NS, bool IN_REGS, bool OUT_REGS>
+__device__ __forceinline__ void fft_passes(float2 (&x)[N / fft_threads(N)], float2* buf,
+                                           const float2* __restrict__ tw) {
   if constexpr (NS < N) {
     constexpr int R = N / NS >= 16 ? 16 : N / NS;
-    stockham_pass<N, NS, R>(buf, tw);
-    fft_passes<N, NS * R>(buf, tw);
+    constexpr int FT = fft_threads(N);
+    constexpr int NB = N / R;
+    constexpr int U = (NB + FT - 1) / FT;
+    constexpr bool LAST = NS * R == N;
+    constexpr bool FROM_REGS = NS == 1 && IN_REGS;
+    constexpr bool TO_REGS = LAST && OUT_REGS;
+    static_assert(!FROM_REGS || regs_ok<N, R>(), "first pass cannot start from registers");
+    static_assert(!TO_REGS || regs_ok<N, R>(), "last pass cannot end in registers");
+    float2 v[U][R];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int j = (int)threadIdx.x + u * FT;
+      if (NB % FT == 0 || j < NB) {
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+          if constexpr (FROM_REGS) v[u][r] = x[u + r * U];
+          else v[u][r] = buf[j + r * NB];
+        }
+        if constexpr (NS > 1) {
+          float2 w[R];
+          twiddle_powers<R>(w, tw, (j % NS) * (N / (NS * R)));
+#pragma unroll
+          for (int r = 1; r < R; ++r) v[u][r] = cmul(v[u][r], w[r]);
+        }
+        dft<R>(v[u]);
+      }
+    }
+    if constexpr (TO_REGS) {
+#pragma unroll
+      for (int u = 0; u < U; ++u)
+#pragma unroll
+        for (int r = 0; r < R; ++r) x[u + r * U] = v[u][r];
+    } else {
+      __syncthreads();
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int j = (int)threadIdx.x + u * FT;
+        if (NB % FT == 0 || j < NB) {
+          const int d = (j / NS) * NS * R + j % NS;
+#pragma unroll
+          for (int r = 0; r < R; ++r) buf[d + r * NS] = v[u][r];
+        }
+      }
+      __syncthreads();
+      fft_passes<N, NS * R, IN_REGS, OUT_REGS>(x, buf, tw);
+    }
   }
 }
 
-// Forward FFT of buf (N points, in LDS) in place; every thread of the
-// workgroup takes part; buf must be complete (synchronised) on entry.
-template <int N>
-__device__ __forceinline__ void fft_lds(float2* buf, const float2* __restrict__ tw) {
-  fft_passes<N, 1>(buf, tw);
+// Forward FFT of N points.  IN: the points are x (thread t holds t + v FT)
+// rather than buf (complete and synchronised).  OUT: the result is left in
+// x rather than in buf (then synchronised).  A transform that starts from
+// registers begins with a barrier, so buf may still be read by the caller's
+// previous loop; one that ends in registers leaves buf to be written only
+// after a barrier.  The register forms fall back to LDS when the pass
+// shapes do not allow them.
+template <int N, bool IN, bool OUT>
+__device__ __forceinline__ void fft(float2 (&x)[N / fft_threads(N)], float2* buf, const float2* __restrict__ tw) {
+  constexpr int FT = fft_threads(N);
+  constexpr bool IN_OK = IN && regs_ok<N, (N >= 16 ? 16 : N)>();
+  constexpr bool OUT_OK = OUT && regs_ok<N, last_radix(N)>();
+  if constexpr (IN && !IN_OK) {
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < N / FT; ++u) buf[threadIdx.x + u * FT] = x[u];
+    __syncthreads();
+  }
+  fft_passes<N, 1, IN_OK, OUT_OK>(x, buf, tw);
+  if constexpr (OUT && !OUT_OK) {
+#pragma unroll
+    for (int u = 0; u < N / FT; ++u) x[u] = buf[threadIdx.x + u * FT];
+  }
 }
 
 // Workgroup -> line pair: consecutive pairs on one XCD (workgroups are
@@ -324,24 +399,31 @@ __device__ __forceinline__ float2 fold_at(const float2* buf, int s, int M, int c
   return w;
 }
 
-// Loads lines a, a + 1 of input term k into buf: the extension w (CONV) or
-// the line at M - 1 .. 2M - 2 (CORR), zero elsewhere.
-template <int N, bool CORR, class In>
-__device__ __forceinline__ void load_pair(float2* buf, const In& in, int k, int a, bool bv, int M, int c0, int refl,
-                                          double scale) {
-  constexpr int FT = fft_threads(N);
-  for (int e = (int)threadIdx.x; e < N; e += FT) {
-    float2 v = make_float2(0.f, 0.f);
-    if constexpr (CORR) {
-      if (e >= M - 1 && e < 2 * M - 1) v = in.get2(k, a, bv, e - (M - 1), scale);
-    } else {
-      if (e < 2 * M - 1) {
-        const int src = ext_src(e + c0 - (M - 1), M, refl);
-        if (src >= 0) v = in.get2(k, a, bv, src, scale);
-      }
+// Point e of the transform input for lines a, a + 1 of term k: the
+// extension w (CONV) or the line at M - 1 .. 2M - 2 (CORR), zero elsewhere.
+template <bool CORR, class In>
+__device__ __forceinline__ float2 input_point(const In& in, int k, int a, bool bv, int e, int M, int c0, int refl,
+                                              double scale) {
+  float2 v = make_float2(0.f, 0.f);
+  if constexpr (CORR) {
+    if (e >= M - 1 && e < 2 * M - 1) v = in.get2(k, a, bv, e - (M - 1), scale);
+  } else {
+    if (e < 2 * M - 1) {
+      const int src = ext_src(e + c0 - (M - 1), M, refl);
+      if (src >= 0) v = in.get2(k, a, bv, src, scale);
     }
-    buf[e] = v;
   }
+  return v;
+}
+
+// The input points a thread holds: x[u] = point t + u FT.
+template <int N, bool CORR, class In>
+__device__ __forceinline__ void fetch_pair(float2 (&x)[N / fft_threads(N)], const In& in, int k, int a, bool bv, int M,
+                                           int c0, int refl, double scale) {
+  constexpr int FT = fft_threads(N);
+#pragma unroll
+  for (int u = 0; u < N / FT; ++u)
+    x[u] = input_point<CORR>(in, k, a, bv, (int)threadIdx.x + u * FT, M, c0, refl, scale);
 }
 
 // One line pair in, one out per term (F1, G1).
@@ -356,27 +438,32 @@ __global__ __launch_bounds__(fft_threads(N)) void fan_out_kernel(In in, Out out,
   if (a >= nlines) return;
   const bool bv = a + 1 < nlines;
   const double scale = in.ss ? 1.0 / sqrt(*in.ss) : 1.0;
-  load_pair<N, CORR>(buf, in, 0, a, bv, M, c0, refl, scale);
-  __syncthreads();
-  fft_lds<N>(buf, tw);
   float2 z[PER];
-#pragma unroll
-  for (int u = 0; u < PER; ++u) z[u] = buf[threadIdx.x + u * FT];
+  fetch_pair<N, CORR>(z, in, 0, a, bv, M, c0, refl, scale);
+  fft<N, true, true>(z, buf, tw);   // the spectrum, point t + u FT in z[u]
   const float inv = 1.0f / (float)N;
   for (int k = 0; k < r; ++k) {
-    __syncthreads();
     const float2* sk = spec + (long)k * N;
+    float2 x[PER];
 #pragma unroll
     for (int u = 0; u < PER; ++u) {
       const int e = (int)threadIdx.x + u * FT;
       const float2 p = CORR ? cmulconj(z[u], sk[e]) : cmul(z[u], sk[e]);
-      buf[e] = make_float2(p.x, -p.y);   // conjugate: the inverse runs as a forward FFT
+      x[u] = make_float2(p.x, -p.y);   // conjugate: the inverse runs as a forward FFT
     }
-    __syncthreads();
-    fft_lds<N>(buf, tw);
-    for (int e = (int)threadIdx.x; e < M; e += FT) {
-      const float2 w = CORR ? fold_at(buf, e, M, c0, refl) : buf[e + M - 1];
-      out.put2(k, a, bv, e, w.x * inv, -w.y * inv);
+    if constexpr (CORR) {            // the fold gathers points of other threads: through LDS
+      fft<N, true, false>(x, buf, tw);
+      for (int e = (int)threadIdx.x; e < M; e += FT) {
+        const float2 w = fold_at(buf, e, M, c0, refl);
+        out.put2(k, a, bv, e, w.x * inv, -w.y * inv);
+      }
+    } else {                         // the crop keeps points M - 1 .. 2M - 2 where they are
+      fft<N, true, true>(x, buf, tw);
+#pragma unroll
+      for (int u = 0; u < PER; ++u) {
+        const int p = (int)threadIdx.x + u * FT;
+        if (p >= M - 1 && p < 2 * M - 1) out.put2(k, a, bv, p - (M - 1), x[u].x * inv, -x[u].y * inv);
+      }
     }
   }
 }
@@ -396,27 +483,36 @@ __global__ __launch_bounds__(fft_threads(N)) void fan_in_kernel(In in, Epi epi, 
 #pragma unroll
   for (int u = 0; u < PER; ++u) acc[u] = make_float2(0.f, 0.f);
   for (int k = 0; k < r; ++k) {
-    if (k) __syncthreads();
-    load_pair<N, CORR>(buf, in, k, a, bv, M, c0, refl, 1.0);
-    __syncthreads();
-    fft_lds<N>(buf, tw);
+    float2 x[PER];
+    fetch_pair<N, CORR>(x, in, k, a, bv, M, c0, refl, 1.0);
+    fft<N, true, true>(x, buf, tw);
     const float2* sk = spec + (long)k * N;
 #pragma unroll
     for (int u = 0; u < PER; ++u) {
       const int e = (int)threadIdx.x + u * FT;
-      acc[u] = cadd(acc[u], CORR ? cmulconj(buf[e], sk[e]) : cmul(buf[e], sk[e]));
+      acc[u] = cadd(acc[u], CORR ? cmulconj(x[u], sk[e]) : cmul(x[u], sk[e]));
     }
   }
-  __syncthreads();
 #pragma unroll
-  for (int u = 0; u < PER; ++u) buf[threadIdx.x + u * FT] = make_float2(acc[u].x, -acc[u].y);
-  __syncthreads();
-  fft_lds<N>(buf, tw);
+  for (int u = 0; u < PER; ++u) acc[u] = make_float2(acc[u].x, -acc[u].y);
   const float inv = 1.0f / (float)N;
-  for (int e = (int)threadIdx.x; e < M; e += FT) {
-    const float2 w = CORR ? fold_at(buf, e, M, c0, refl) : buf[e + M - 1];
-    epi.put(a, e, w.x * inv);
-    if (bv) epi.put(a + 1, e, -w.y * inv);
+  if constexpr (CORR) {
+    fft<N, true, false>(acc, buf, tw);
+    for (int e = (int)threadIdx.x; e < M; e += FT) {
+      const float2 w = fold_at(buf, e, M, c0, refl);
+      epi.put(a, e, w.x * inv);
+      if (bv) epi.put(a + 1, e, -w.y * inv);
+    }
+  } else {
+    fft<N, true, true>(acc, buf, tw);
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+      const int p = (int)threadIdx.x + u * FT;
+      if (p >= M - 1 && p < 2 * M - 1) {
+        epi.put(a, p - (M - 1), acc[u].x * inv);
+        if (bv) epi.put(a + 1, p - (M - 1), -acc[u].y * inv);
+      }
+    }
   }
 }
 
@@ -427,10 +523,15 @@ __global__ __launch_bounds__(fft_threads(N)) void spectrum_kernel(const double* 
   constexpr int FT = fft_threads(N);
   __shared__ float2 buf[N];
   const int k = (int)blockIdx.x;
-  for (int e = (int)threadIdx.x; e < N; e += FT) buf[e] = make_float2(e < M ? (float)gen[(long)k * M + e] : 0.f, 0.f);
-  __syncthreads();
-  fft_lds<N>(buf, tw);
-  for (int e = (int)threadIdx.x; e < N; e += FT) spec[(long)k * N + e] = buf[e];
+  float2 x[N / FT];
+#pragma unroll
+  for (int u = 0; u < N / FT; ++u) {
+    const int e = (int)threadIdx.x + u * FT;
+    x[u] = make_float2(e < M ? (float)gen[(long)k * M + e] : 0.f, 0.f);
+  }
+  fft<N, true, true>(x, buf, tw);
+#pragma unroll
+  for (int u = 0; u < N / FT; ++u) spec[(long)k * N + threadIdx.x + u * FT] = x[u];
 }
 
 // Bobs (m x n, FP64) -> Bobs^T (n x ld, FP32).
