@@ -101,13 +101,38 @@ __global__ void weight_zero_kernel(const double* P, double* Pb, int m, int n, in
   }
 }
 
-// column sums of X (m x n) over even rows and odd rows: ev[b], od[b]
-__global__ void colsum_parity_kernel(const double* X, int m, int n, double* ev, double* od) {
+// Column sums of X (m x n) over even rows and odd rows, in two steps with a
+// fixed order (deterministic): block (bx, by) sums rows [by RW, (by + 1) RW)
+// of 64 columns, 4 row phases per column, into part[by][b][parity]; then
+// colsum_finish_kernel adds the CS_RB chunks of each column in order.
+constexpr int CS_RB = 16;
+
+__global__ __launch_bounds__(256) void colsum_partial_kernel(const double* X, int m, int n, double* part) {
+  __shared__ double sh[4][64][2];
+  const int col = blockIdx.x * 64 + (threadIdx.x & 63), g = threadIdx.x >> 6;
+  const int rw = (m + CS_RB - 1) / CS_RB;
+  const int a0 = blockIdx.y * rw, a1 = min(m, a0 + rw);
+  double v[2] = {0.0, 0.0};
+  if (col < n)
+    for (int a = a0 + g; a < a1; a += 4) v[a & 1] += X[(long)a * n + col];
+  sh[g][threadIdx.x & 63][0] = v[0];
+  sh[g][threadIdx.x & 63][1] = v[1];
+  __syncthreads();
+  if (g == 0 && col < n) {
+    const int c = threadIdx.x;
+    part[((long)blockIdx.y * n + col) * 2 + 0] = ((sh[0][c][0] + sh[1][c][0]) + sh[2][c][0]) + sh[3][c][0];
+    part[((long)blockIdx.y * n + col) * 2 + 1] = ((sh[0][c][1] + sh[1][c][1]) + sh[2][c][1]) + sh[3][c][1];
+  }
+}
+
+__global__ void colsum_finish_kernel(const double* part, int n, double* ev, double* od) {
   const int b = blockIdx.x * blockDim.x + threadIdx.x;
   if (b >= n) return;
   double se = 0.0, so = 0.0;
-  for (int a = 0; a < m; a += 2) se += X[(long)a * n + b];
-  for (int a = 1; a < m; a += 2) so += X[(long)a * n + b];
+  for (int q = 0; q < CS_RB; ++q) {
+    se += part[((long)q * n + b) * 2 + 0];
+    so += part[((long)q * n + b) * 2 + 1];
+  }
   ev[b] = se;
   od[b] = so;
 }
@@ -228,6 +253,80 @@ __global__ __launch_bounds__(ST) void mgs2_kernel(double* Y, int p, int d) {
       __syncthreads();
     }
   }
+}
+
+// The same orthonormalisation for up to PC columns of length up to
+// EPT * CT (CT = 512 threads), held in registers: classical Gram-Schmidt applied twice, so the
+// projections of a column on all previous ones are one batched block
+// reduction and its norm another (4p reductions, against about p^2 in the
+// modified form, and no memory traffic between them).  Two passes give
+// orthogonality at rounding level; dependent columns are zeroed by the same
+// rule as mgs2_kernel.
+// Column C of one pass (a compile-time recursion over the columns, so every
+// register index is a constant).
+template <int C, int PC, int EPT>
+__device__ __forceinline__ void cgs2_column(double (&y)[PC][EPT], int p, double* sh) {
+  if constexpr (C < PC) {
+    if (C >= p) return;
+    double dots[C + 1];   // dots[j], j < C: <y_C, y_j>; dots[C]: ||y_C||^2 before projection
+#pragma unroll
+    for (int j = 0; j <= C; ++j) {
+      double a = 0.0;
+#pragma unroll
+      for (int q = 0; q < EPT; ++q) a += y[C][q] * y[j][q];
+      dots[j] = a;
+    }
+    block_allreduce<C + 1>(dots, sh);
+    const double v0 = dots[C];
+#pragma unroll
+    for (int j = 0; j < C; ++j)
+#pragma unroll
+      for (int q = 0; q < EPT; ++q) y[C][q] -= dots[j] * y[j][q];
+    double nv[1] = {0.0};
+#pragma unroll
+    for (int q = 0; q < EPT; ++q) nv[0] += y[C][q] * y[C][q];
+    block_allreduce<1>(nv, sh);
+    const double inv = (nv[0] > 1e-20 * v0 && nv[0] > 0.0) ? 1.0 / sqrt(nv[0]) : 0.0;
+#pragma unroll
+    for (int q = 0; q < EPT; ++q) y[C][q] *= inv;
+    cgs2_column<C + 1, PC, EPT>(y, p, sh);
+  }
+}
+
+constexpr int CT = 512;   // threads of the register Gram-Schmidt kernel
+
+template <int PC, int EPT>
+__global__ __launch_bounds__(CT) void cgs2_kernel(double* Y, int p, int d) {
+  __shared__ double sh[(PC + 1) * 32];
+  double y[PC][EPT];
+#pragma unroll
+  for (int c = 0; c < PC; ++c)
+#pragma unroll
+    for (int q = 0; q < EPT; ++q) {
+      const int t = (int)threadIdx.x + q * CT;
+      y[c][q] = (c < p && t < d) ? Y[(long)c * d + t] : 0.0;
+    }
+  cgs2_column<0, PC, EPT>(y, p, sh);
+  cgs2_column<0, PC, EPT>(y, p, sh);
+#pragma unroll
+  for (int c = 0; c < PC; ++c)
+#pragma unroll
+    for (int q = 0; q < EPT; ++q) {
+      const int t = (int)threadIdx.x + q * CT;
+      if (c < p && t < d) Y[(long)c * d + t] = y[c][q];
+    }
+}
+
+// Orthonormalises the p columns (length d) of Y in place.
+void orthonormalise(double* Y, int p, int d, hipStream_t s) {
+  if (p <= 16 && d <= CT)
+    hipLaunchKernelGGL((cgs2_kernel<16, 1>), dim3(1), dim3(CT), 0, s, Y, p, d);
+  else if (p <= 16 && d <= 2 * CT)
+    hipLaunchKernelGGL((cgs2_kernel<16, 2>), dim3(1), dim3(CT), 0, s, Y, p, d);
+  else if (p <= 16 && d <= 4 * CT)
+    hipLaunchKernelGGL((cgs2_kernel<16, 4>), dim3(1), dim3(CT), 0, s, Y, p, d);
+  else
+    hipLaunchKernelGGL(mgs2_kernel, dim3(1), dim3(ST), 0, s, Y, p, d);
 }
 
 // One-sided (Hestenes) Jacobi on the p columns of Z (length d): rotates
@@ -434,6 +533,7 @@ int kron_impl(const double* P, int m, int n, int l, int q, int bc, int r, double
   double* Pb = (double*)ar.alloc_zero(mn * 8, s);
   double* Pt = (double*)ar.alloc_zero(mn * 8, s);
   double* tmp = (double*)ar.alloc_zero(mn * 8, s);
+  double* colpart = (double*)ar.alloc_zero((size_t)CS_RB * n * 2 * 8, s);
   double* vecs = (double*)ar.alloc_zero((size_t)4 * (m + n) * 8, s);
   double* Yc = (double*)ar.alloc_zero((size_t)PMAX * m * 8, s);
   double* Zc = (double*)ar.alloc_zero((size_t)PMAX * n * 8, s);
@@ -445,7 +545,7 @@ int kron_impl(const double* P, int m, int n, int l, int q, int bc, int r, double
   double* gh = (double*)ar.alloc_zero((size_t)r * m * 8, s);
   double* gk = (double*)ar.alloc_zero((size_t)r * n * 8, s);
   double* red = (double*)ar.alloc_zero((RED_BLOCKS + 8) * 8, s);
-  if (!(Pb && Pt && tmp && vecs && Yc && Zc && Wm && sig && order && U && V && gh && gk && red))
+  if (!(Pb && Pt && tmp && colpart && vecs && Yc && Zc && Wm && sig && order && U && V && gh && gk && red))
     return set_error(SFISTA_ERR_NOMEM, "device allocation failed (%s)", ar.last_error());
   double* sig_out = sig + PMAX;
 
@@ -455,7 +555,8 @@ int kron_impl(const double* P, int m, int n, int l, int q, int bc, int r, double
     hipLaunchKernelGGL(weight_zero_kernel, ew, et, 0, s, P, Pb, m, n, l, q);
   } else {
     double *ev = vecs, *od = vecs + (m + n);
-    hipLaunchKernelGGL(colsum_parity_kernel, dim3((n + 255) / 256), dim3(256), 0, s, P, m, n, ev, od);
+    hipLaunchKernelGGL(colsum_partial_kernel, dim3((n + 63) / 64, CS_RB), dim3(256), 0, s, P, m, n, colpart);
+    hipLaunchKernelGGL(colsum_finish_kernel, dim3((n + 255) / 256), dim3(256), 0, s, colpart, n, ev, od);
     hipLaunchKernelGGL(left_root_kernel, ew, et, 0, s, P, tmp, m, n, rm, ev, od);
     hipLaunchKernelGGL(rowsum_parity_kernel, dim3(m), dim3(256), 0, s, tmp, m, n, ev, od);
     hipLaunchKernelGGL(right_root_kernel, ew, et, 0, s, tmp, Pb, m, n, rn, ev, od);
@@ -466,9 +567,9 @@ int kron_impl(const double* P, int m, int n, int l, int q, int bc, int r, double
   hipLaunchKernelGGL(hash_fill_kernel, ew, et, 0, s, Zc, (long)p * n, 0x51f15eedull);
   for (int it = 0; it < SUBSPACE_ITERS; ++it) {
     hipLaunchKernelGGL(mat_cols_kernel, dim3(m), dim3(KT), 0, s, Pb, m, n, Zc, p, Yc);
-    hipLaunchKernelGGL(mgs2_kernel, dim3(1), dim3(ST), 0, s, Yc, p, m);
+    orthonormalise(Yc, p, m, s);
     hipLaunchKernelGGL(mat_cols_kernel, dim3(n), dim3(KT), 0, s, Pt, n, m, Yc, p, Zc);
-    if (it + 1 < SUBSPACE_ITERS) hipLaunchKernelGGL(mgs2_kernel, dim3(1), dim3(ST), 0, s, Zc, p, n);
+    if (it + 1 < SUBSPACE_ITERS) orthonormalise(Zc, p, n, s);
   }
   // Z = P_bar^T Y with Y orthonormal: P_bar ~ Y Z^T; SVD of Z by one-sided Jacobi
   hipLaunchKernelGGL(jacobi_kernel, dim3(1), dim3(ST), 0, s, Zc, p, n, Wm, sig, order);
