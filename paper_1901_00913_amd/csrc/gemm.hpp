@@ -317,6 +317,7 @@ using Tile256 = Tile<SF_TILE_BM, SF_TILE_BN, SF_TILE_WM, SF_TILE_WN>;
 using Tile256 = Tile<256, 256, 128, 64>;
 #endif
 using Tile128 = Tile<128, 128, 64, 32>;
+using Tile320 = Tile<320, 256, 160, 64>;   // 2-plane modes only (72 copies per stage over 8 waves)
 using TileS = Tile<64, 64, 32, 32>;
 
 template <int MODE> struct BigTile { using T = Tile256; };
@@ -514,6 +515,7 @@ struct GemmPlanDev {
   const PlanItem* items = nullptr;
   const int2* split_tiles = nullptr;
   int nitems = 0, nsplit = 0, S = 1, kchunk = 0;
+  int tile320 = 0;
 };
 
 // Launch of a planned product: the tile pass, then (with split tiles) the
@@ -525,6 +527,14 @@ hipError_t launch_planned(GemmArgs g, const Epi& epi, const GemmPlanDev& pl, typ
   using Acc = typename ModeTraits<MODE>::Acc;
   if (g.M <= 0 || g.N <= 0 || pl.nitems == 0) return hipSuccess;
   g.kchunk = pl.kchunk;
+  if constexpr (ModeTraits<MODE>::planes == 2) {
+    if (pl.tile320) {
+      hipLaunchKernelGGL((gemm_planned_kernel<MODE, Tile320, Epi>), dim3(pl.nitems), dim3(Tile320::THREADS), 0, s, g,
+                         epi, ws, pl.S, pl.items);
+      if (mid) (void)hipEventRecord(mid, s);
+      return hipGetLastError();
+    }
+  }
   hipLaunchKernelGGL((gemm_planned_kernel<MODE, T, Epi>), dim3(pl.nitems), dim3(T::THREADS), 0, s, g, epi, ws,
                      pl.S, pl.items);
   if (mid) (void)hipEventRecord(mid, s);

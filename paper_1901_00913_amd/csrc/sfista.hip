@@ -58,8 +58,10 @@ hipError_t collect_times(sfista_plan* h) {
     if ((e = hipEventElapsedTime(&r, h->ev_pool[mk.second + 1], h->ev_pool[mk.second + 2])) != hipSuccess) return e;
     h->t_sum[mk.first] += g;
     h->t_cnt[mk.first] += 1;
-    h->t_sum[4 + mk.first] += r;
-    h->t_cnt[4 + mk.first] += 1;
+    if (h->pl[mk.first].nsplit > 0) {   // products without split tiles launch no reduction
+      h->t_sum[4 + mk.first] += r;
+      h->t_cnt[4 + mk.first] += 1;
+    }
   }
   h->ev_marks.clear();
   h->ev_used = 0;
@@ -229,8 +231,19 @@ int setup_mode(sfista_plan* h, const double* Bobs, const double* A, const double
         plan_gemm<TB>((int)rn, m, gemm_kstages<MODE>(n), slots), plan_gemm<TB>(n, m, gemm_kstages<MODE>((int)rm), slots),
         plan_gemm<TB>((int)rm, n, gemm_kstages<MODE>(m), slots), plan_gemm<TB>(m, n, gemm_kstages<MODE>((int)rn), slots)};
     size_t ws_elems = 0;
+    GemmPlan alt[4];
+    bool use320[4] = {false, false, false, false};
+    if constexpr (ModeTraits<MODE>::planes == 2) {
+      const int Ms[4] = {(int)rn, n, (int)rm, m}, Ns[4] = {m, m, n, n}, Ks[4] = {n, (int)rm, m, (int)rn};
+      for (int q = 0; q < 4; ++q) {
+        if (Ms[q] % 320) continue;
+        alt[q] = plan_gemm<Tile320>(Ms[q], Ns[q], gemm_kstages<MODE>(Ks[q]), cus);
+        use320[q] = alt[q].split_tiles.empty() && plans[q].split_tiles.size() > 0;
+      }
+    }
     for (int q = 0; q < 4; ++q) {
-      const GemmPlan& gp = plans[q];
+      const GemmPlan& gp = use320[q] ? alt[q] : plans[q];
+      h->pl[q].tile320 = use320[q] ? 1 : 0;
       GemmPlanDev& pd = h->pl[q];
       PlanItem* items = static_cast<PlanItem*>(h->mem->alloc_zero(gp.items.size() * sizeof(PlanItem), h->s));
       int2* tiles = gp.split_tiles.empty()

@@ -310,3 +310,21 @@ def test_config3_fullsize_first_iterations(sf):
     say(f"[cfg3] bf16x3 5 iterations rel err {e:.3e}")
     assert e < 1e-5
     s.close()
+
+
+def test_kernel_times_report_each_launch(sf):
+    """Per-kernel timing: every timed solve launches each of the four GEMMs
+    once per iteration; a product whose plan has no split tiles reports no
+    reduction (0 launches, 0 ms), the others one per GEMM launch."""
+    p = S.config(2, n=512)
+    K, H = _oracle_setup(p)
+    s = sf.Solver(dev(p.bobs), dev(K), dev(H), lam=p.lam, L=1.0, precision="bf16x3")
+    s.set_timing(True)
+    s.solve(10, want_x=False)
+    ms, cnt = s.kernel_times()
+    assert cnt[:4] == [10, 10, 10, 10]
+    assert all(t > 0.0 for t in ms[:4])
+    for g in range(4):
+        assert cnt[4 + g] in (0, 10)
+        assert (ms[4 + g] > 0.0) == (cnt[4 + g] == 10)
+    s.close()
