@@ -74,6 +74,9 @@ def test_generators_match_oracle(sf, m, n, l, q, bc, sig, theta):
     (200, 136, 3, 100, 68, O.BC_ZERO),
     (257, 130, 2, 128, 65, O.BC_REFLEXIVE),
     (33, 1030, 2, 16, 515, O.BC_REFLEXIVE),
+    (600, 40, 2, 599, 20, O.BC_REFLEXIVE),     # 2048-point column transforms
+    (9, 2100, 1, 4, 0, O.BC_ZERO),             # 8192-point row transforms (512 threads)
+    (2049, 6, 1, 1024, 5, O.BC_REFLEXIVE),     # 8192-point column transforms
 ])
 def test_operator_matches_oracle(sf, m, n, r, l, q, bc):
     """A_s X and A_s^T A_s X with random generators (full Toeplitz and
