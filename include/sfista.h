@@ -203,9 +203,16 @@ int sfista_batch_setup(const sfista_batch_item* items, int count, const sfista_p
  * Synchronous. */
 int sfista_batch_solve(sfista_batch_handle h, int iters, double* const* X_out, sfista_report* reps);
 
-/* Tile shape chosen per product (host, 4 entries: F1, F2, G1, G2); 0 = 128 x 128
- * tiles of 8 waves, 1 = 64 x 64 tiles of 4 waves. */
+/* Tile shape chosen per product (host, 4 entries: F1, F2, G1, G2): 0 = the
+ * mode's large tile (256 x 256, 8 waves; 128 x 128 in FP64), 1 = 64 x 64
+ * tiles of 4 waves, 2 = 128 x 128 tiles of 8 waves (not in FP64). */
 int sfista_batch_tiles(sfista_batch_handle h, int* choice);
+
+/* Pin the tile shape of each product (host, 4 entries, codes as above; 2 is
+ * refused in FP64).  The iterates do not depend on the shapes (every tile
+ * takes the whole K in the same order).  Drops a captured graph, which is
+ * captured again at the next solve.  Synchronises the batch's stream. */
+int sfista_batch_set_tiles(sfista_batch_handle h, const int* choice);
 
 void sfista_batch_destroy(sfista_batch_handle h);
 

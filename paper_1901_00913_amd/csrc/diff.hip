@@ -235,7 +235,7 @@ struct sfista_diff {
   GemmArgs* dargs[7] = {};
   WorkItem* dwork[7] = {};
   int nwork[7] = {};
-  int choice[7] = {};                       // 0 = the mode's big tile, 1 = TileS
+  int choice[7] = {};                       // 0 = the mode's big tile, 1 = TileS, 2 = Tile128
   void* ep[7] = {};                         // epilogue tables (see diff_build)
   bool forward_done = false;
   DeviceArena arena;
@@ -317,11 +317,16 @@ int diff_build(sfista_diff* d) {
   for (int q = 0; q < 7; ++q) {
     if (!(d->dargs[q] = static_cast<GemmArgs*>(upload(args[q].data(), sizeof(GemmArgs) * cnt))))
       return set_error(SFISTA_ERR_NOMEM, "device allocation failed");
-    // the 256 x 256 tile only when it alone fills the GPU twice over
-    long big = 0;
-    for (const GemmArgs& g : args[q]) big += (long)((g.M + TB::BM - 1) / TB::BM) * ((g.N + TB::BN - 1) / TB::BN);
-    d->choice[q] = big >= 2L * slots ? 0 : 1;
-    const int BM = d->choice[q] ? TileS::BM : TB::BM, BN = d->choice[q] ? TileS::BN : TB::BN;
+    // the largest tile whose tiles alone fill the GPU twice over: the mode's
+    // big tile, then 128 x 128, then 64 x 64
+    auto count = [&](int bm, int bn) {
+      long t = 0;
+      for (const GemmArgs& g : args[q]) t += (long)((g.M + bm - 1) / bm) * ((g.N + bn - 1) / bn);
+      return t;
+    };
+    d->choice[q] = count(TB::BM, TB::BN) >= 2L * slots ? 0 : count(Tile128::BM, Tile128::BN) >= 2L * cus ? 2 : 1;
+    const int BM = d->choice[q] == 0 ? TB::BM : d->choice[q] == 2 ? Tile128::BM : TileS::BM;
+    const int BN = d->choice[q] == 0 ? TB::BN : d->choice[q] == 2 ? Tile128::BN : TileS::BN;
     std::vector<int> order(cnt);
     for (int i = 0; i < cnt; ++i) order[i] = i;
     std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return args[q][x].K > args[q][y].K; });
@@ -396,6 +401,7 @@ hipError_t grouped(sfista_diff* d, int q, const void* epis) {
 template <int MODE, class Epi>
 hipError_t product(sfista_diff* d, int q, int table, long index) {
   const void* epis = static_cast<const Epi*>(d->ep[table]) + index * d->count;
+  if (d->choice[q] == 2) return grouped<MODE, Tile128, Epi>(d, q, epis);
   return d->choice[q] ? grouped<MODE, TileS, Epi>(d, q, epis)
                       : grouped<MODE, typename BigTile<MODE>::T, Epi>(d, q, epis);
 }

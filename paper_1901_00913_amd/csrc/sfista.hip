@@ -554,9 +554,9 @@ struct sfista_batch {
   DeviceArena arena;
   GemmArgs* dargs[4] = {};          // per product: device array of GEMM arguments (one per problem)
   void* depi[4] = {};               // per product: device array of epilogues
-  WorkItem* dwork[4][2] = {};       // per product and tile shape: work list
-  int nwork[4][2] = {};
-  int choice[4] = {0, 0, 0, 0};     // 0 = the mode's big tile, 1 = TileS
+  WorkItem* dwork[4][3] = {};       // per product and tile shape: work list
+  int nwork[4][3] = {};
+  int choice[4] = {0, 0, 0, 0};     // 0 = the mode's big tile, 1 = TileS, 2 = Tile128
   double* beta = nullptr;           // beta[k] = (t_k - 1) / t_{k+1}, beta[0] = 0
   int* counter = nullptr;           // iterations completed (device)
   hipGraphExec_t gexec = nullptr;
@@ -575,12 +575,19 @@ namespace {
 
 constexpr int GRAPH_ITERS = 10;
 
-template <class T>
-int tile_shape_index() { return std::is_same<T, TileS>::value ? 1 : 0; }
+template <int MODE, class T>
+int tile_shape_index() {
+  if (std::is_same<T, TileS>::value) return 1;
+  return std::is_same<T, typename BigTile<MODE>::T>::value ? 0 : 2;
+}
+
+// Tile shape c exists in this mode (FP64's big tile is already 128 x 128).
+template <int MODE>
+bool shape_offered(int c) { return c != 2 || !std::is_same<typename BigTile<MODE>::T, Tile128>::value; }
 
 template <int MODE, class T, class Epi>
 hipError_t launch_grouped(sfista_batch* b, int prod) {
-  const int c = tile_shape_index<T>();
+  const int c = tile_shape_index<MODE, T>();
   if (b->nwork[prod][c] == 0) return hipSuccess;
   hipLaunchKernelGGL((gemm_grouped_kernel<MODE, T, Epi>), dim3(b->nwork[prod][c]), dim3(T::THREADS), 0, b->s,
                      b->dargs[prod], static_cast<const Epi*>(b->depi[prod]), b->dwork[prod][c]);
@@ -589,6 +596,7 @@ hipError_t launch_grouped(sfista_batch* b, int prod) {
 
 template <int MODE, class Epi>
 hipError_t launch_product(sfista_batch* b, int prod) {
+  if (b->choice[prod] == 2) return launch_grouped<MODE, Tile128, Epi>(b, prod);
   return b->choice[prod] ? launch_grouped<MODE, TileS, Epi>(b, prod)
                          : launch_grouped<MODE, typename BigTile<MODE>::T, Epi>(b, prod);
 }
@@ -664,9 +672,11 @@ int batch_build(sfista_batch* b) {
     std::vector<int> order(cnt);
     for (int i = 0; i < cnt; ++i) order[i] = i;
     std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return args[q][x].K > args[q][y].K; });
-    for (int c = 0; c < 2; ++c) {
+    for (int c = 0; c < 3; ++c) {
       using TB = typename BigTile<MODE>::T;
-      const int BM = c ? TileS::BM : TB::BM, BN = c ? TileS::BN : TB::BN;
+      if (!shape_offered<MODE>(c)) continue;
+      const int BM = c == 0 ? TB::BM : c == 1 ? TileS::BM : Tile128::BM;
+      const int BN = c == 0 ? TB::BN : c == 1 ? TileS::BN : Tile128::BN;
       std::vector<WorkItem> w;
       for (int i : order) {
         const int tm_n = (args[q][i].M + BM - 1) / BM, tn_n = (args[q][i].N + BN - 1) / BN;
@@ -681,8 +691,8 @@ int batch_build(sfista_batch* b) {
   return SFISTA_OK;
 }
 
-// Times both tile shapes of every product on the batch itself and keeps the
-// faster; the state is reset afterwards.
+// Times the tile shapes of every product on the batch itself and keeps the
+// fastest; the state is reset afterwards.
 template <int MODE>
 hipError_t batch_autotune(sfista_batch* b) {
   hipEvent_t e0, e1;
@@ -692,7 +702,8 @@ hipError_t batch_autotune(sfista_batch* b) {
   for (int q = 0; q < 4; ++q) {
     float best = 1e30f;
     int pick = 0;
-    for (int c = 0; c < 2; ++c) {
+    for (int c = 0; c < 3; ++c) {
+      if (!shape_offered<MODE>(c)) continue;
       b->choice[q] = c;
       for (int rep = 0; rep < 4; ++rep) {
         if (rep == 1) (void)hipEventRecord(e0, b->s);
@@ -739,7 +750,7 @@ bool tune_cache_lookup(const std::string& key, int* choice) {
     std::string k;
     int c[4];
     if ((ls >> k >> c[0] >> c[1] >> c[2] >> c[3]) && k == key) {
-      for (int q = 0; q < 4; ++q) choice[q] = c[q] ? 1 : 0;
+      for (int q = 0; q < 4; ++q) choice[q] = (c[q] >= 0 && c[q] <= 2) ? c[q] : 1;
       return true;
     }
   }
@@ -757,12 +768,15 @@ template <int MODE>
 int batch_setup_mode(sfista_batch* b) {
   int rc = batch_build<MODE>(b);
   if (rc != SFISTA_OK) return rc;
-  // default shape: the 128 x 128 tile unless it leaves most CUs idle
+  // default shape: the largest tile whose tiles fill the GPU twice over
   int cus = 256, dev = 0;
   hipDeviceProp_t prop;
   if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess) cus = prop.multiProcessorCount;
   const int slots = cus * resident_per_cu<MODE>();
-  for (int q = 0; q < 4; ++q) b->choice[q] = b->nwork[q][0] >= 2 * slots ? 0 : 1;
+  for (int q = 0; q < 4; ++q)
+    b->choice[q] = b->nwork[q][0] >= 2 * slots ? 0 : (shape_offered<MODE>(2) && b->nwork[q][2] >= 2 * cus) ? 2 : 1;
+  for (int q = 0; q < 4; ++q)
+    if (!shape_offered<MODE>(b->choice[q])) b->choice[q] = 1;
   if (b->flags & SFISTA_BATCH_AUTOTUNE) {
     const std::string key = batch_key(b);
     if (!tune_cache_lookup(key, b->choice)) {
@@ -928,6 +942,23 @@ int sfista_batch_tiles(sfista_batch_handle b, int* choice) {
   clear_error();
   if (!b || !choice) return set_error(SFISTA_ERR_ARG, "NULL argument");
   for (int q = 0; q < 4; ++q) choice[q] = b->choice[q];
+  return SFISTA_OK;
+}
+
+int sfista_batch_set_tiles(sfista_batch_handle b, const int* choice) {
+  clear_error();
+  if (!b || !choice) return set_error(SFISTA_ERR_ARG, "NULL argument");
+  for (int q = 0; q < 4; ++q) {
+    const bool ok = choice[q] >= 0 && choice[q] <= 2 &&
+                    (b->mode != M_F64 || choice[q] != 2);   // FP64's big tile is the 128 x 128 one
+    if (!ok) return set_error(SFISTA_ERR_ARG, "tile shape %d of product %d is not offered", choice[q], q);
+  }
+  hipError_t e = hipStreamSynchronize(b->s);
+  if (e != hipSuccess) return hip_fail(e, "sfista_batch_set_tiles");
+  for (int q = 0; q < 4; ++q) b->choice[q] = choice[q];
+  // a captured graph holds the old launch shapes
+  if (b->gexec) { (void)hipGraphExecDestroy(b->gexec); b->gexec = nullptr; }
+  if (b->graph) { (void)hipGraphDestroy(b->graph); b->graph = nullptr; }
   return SFISTA_OK;
 }
 

@@ -33,7 +33,7 @@ PRECISIONS = {"fp64": 0, "fp32": 1, "bf16": 2, "fp16": 3, "bf16x3": 4}
 EXPORTS = ("kron_approx", "sfista_setup", "sfista_step", "sfista_solve", "sfista_apply",
            "sfista_set_timing", "sfista_kernel_times", "sfista_get_L", "sfista_destroy",
            "sfista_last_error", "sfista_batch_setup", "sfista_batch_solve", "sfista_batch_tiles",
-           "sfista_batch_destroy", "sfista_diff_setup", "sfista_diff_forward", "sfista_diff_backward",
+           "sfista_batch_destroy", "sfista_batch_set_tiles", "sfista_diff_setup", "sfista_diff_forward", "sfista_diff_backward",
            "sfista_diff_get_L", "sfista_diff_destroy", "sfista_diff_update", "sfista_release_cached",
            "kron_generators", "sfista_fft_setup", "sfista_fft_step", "sfista_fft_solve", "sfista_fft_apply",
            "sfista_fft_get_L", "sfista_fft_destroy")
@@ -95,6 +95,7 @@ def lib() -> ctypes.CDLL:
                                      ctypes.POINTER(vp)]
     L.sfista_batch_solve.argtypes = [vp, i, ctypes.POINTER(vp), ctypes.POINTER(Report)]
     L.sfista_batch_tiles.argtypes = [vp, ctypes.POINTER(i)]
+    L.sfista_batch_set_tiles.argtypes = [vp, ctypes.POINTER(i)]
     L.sfista_batch_destroy.argtypes = [vp]
     L.sfista_batch_destroy.restype = None
     L.sfista_diff_setup.argtypes = [ctypes.POINTER(BatchItem), i, i, i, i, vp, ctypes.POINTER(vp)]
@@ -118,7 +119,7 @@ def lib() -> ctypes.CDLL:
     L.sfista_last_error.restype = ctypes.c_char_p
     for name in ("kron_approx", "sfista_setup", "sfista_step", "sfista_solve", "sfista_apply", "sfista_get_L",
                  "sfista_set_timing", "sfista_kernel_times", "sfista_batch_setup", "sfista_batch_solve",
-                 "sfista_batch_tiles", "sfista_diff_setup", "sfista_diff_forward", "sfista_diff_backward",
+                 "sfista_batch_tiles", "sfista_batch_set_tiles", "sfista_diff_setup", "sfista_diff_forward", "sfista_diff_backward",
                  "sfista_diff_get_L", "sfista_diff_update", "sfista_release_cached", "kron_generators",
                  "sfista_fft_setup", "sfista_fft_step", "sfista_fft_solve", "sfista_fft_apply", "sfista_fft_get_L"):
         getattr(L, name).restype = ctypes.c_int
@@ -321,7 +322,7 @@ class Batch:
     each): every GEMM phase of one iteration is a single grouped launch over
     all problems.  ``problems`` is a sequence of ``(Bobs, A, B, lam, L)`` with
     device float64 tensors; ``L = None`` estimates it by ``power_iters`` power
-    steps.  ``autotune`` times both tile shapes per phase on the batch itself;
+    steps.  ``autotune`` times the tile shapes of each phase on the batch itself;
     ``graph`` replays the iterations from a captured HIP graph."""
 
     def __init__(self, problems, precision: str = "bf16x3", max_iters: int = 1000, nonneg: bool = False,
@@ -359,10 +360,16 @@ class Batch:
         return xs, [r.as_dict() for r in reps]
 
     def tiles(self):
-        """Tile shape chosen per phase (F1, F2, G1, G2): 0 = 128 x 128, 1 = 64 x 64."""
+        """Tile shape chosen per phase (F1, F2, G1, G2): 0 = the mode's large
+        tile (256 x 256; 128 x 128 in FP64), 1 = 64 x 64, 2 = 128 x 128."""
         c = (ctypes.c_int * 4)()
         _check(lib().sfista_batch_tiles(self._h, c))
         return list(c)
+
+    def set_tiles(self, choice):
+        """Pin the tile shape of each phase (codes as in ``tiles``)."""
+        c = (ctypes.c_int * 4)(*[int(v) for v in choice])
+        _check(lib().sfista_batch_set_tiles(self._h, c))
 
     def close(self):
         if self._h is not None:

@@ -130,6 +130,7 @@ def test_batch_calls_reject_null(L):
     assert L.sfista_batch_setup(_items(), 2, ctypes.byref(p), 10, 0, None, None) == -1
     assert L.sfista_batch_solve(None, 1, None, None) == -1
     assert L.sfista_batch_tiles(None, (ctypes.c_int * 4)()) == -1
+    assert L.sfista_batch_set_tiles(None, (ctypes.c_int * 4)()) == -1
     L.sfista_batch_destroy(None)
 
 

@@ -153,7 +153,7 @@ def test_autotune_cache_and_tile_invariance(sf, case, tmp_path, monkeypatch):
     probs = _problems(case)
     b1 = sf.Batch(probs, precision="bf16x3", max_iters=ITERS, autotune=True)
     t1 = b1.tiles()
-    assert all(c in (0, 1) for c in t1)
+    assert all(c in (0, 1, 2) for c in t1)
     lines = cache.read_text().splitlines()
     assert len(lines) == 1
     X1, _ = b1.solve(ITERS)
@@ -169,6 +169,32 @@ def test_autotune_cache_and_tile_invariance(sf, case, tmp_path, monkeypatch):
     b3.close()
     for a, c in zip(X1, X3):
         assert np.array_equal(host(a), host(c))
+
+
+def test_pinned_tile_shapes_are_bitwise_equal(sf, case):
+    """Every tile shape (the large tile, 64 x 64, 128 x 128) pinned for all
+    four products gives the same iterates bit for bit, in eager launches and
+    through a graph captured after the change; FP64 refuses the shape that
+    is its own large tile."""
+    probs = _problems(case)
+    outs = []
+    for shape in (0, 1, 2):
+        for graph in (False, True):
+            b = sf.Batch(probs, precision="fp32", max_iters=ITERS, graph=graph)
+            b.solve(2)                      # a graph is captured with the default shapes first
+            b.set_tiles([shape] * 4)
+            assert b.tiles() == [shape] * 4
+            X, _ = b.solve(ITERS - 2)
+            outs.append([host(x) for x in X])
+            b.close()
+    for o in outs[1:]:
+        for a, c in zip(outs[0], o):
+            assert np.array_equal(a, c)
+    b = sf.Batch(probs[:2], precision="fp64", max_iters=2)
+    with pytest.raises(sf.SfistaError):
+        b.set_tiles([2, 2, 2, 2])
+    b.set_tiles([1, 0, 1, 0])
+    b.close()
 
 
 def test_batch_iteration_limit(sf, case):

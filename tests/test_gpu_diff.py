@@ -229,3 +229,39 @@ def test_autograd_reuses_plan(sf):
         assert np.array_equal(grads[0][1], grads[1][1])
         assert grads[0][2] == grads[1][2]
     plan.close()
+
+
+def test_fp32_batch_512_uses_mid_tiles(sf):
+    """The batch shape of the benchmark (8 images at 512^2, r = 4), short
+    unroll: the term-stacked products and the factor-gradient products run on
+    128 x 128 tiles there (their 64 x 64 and 256 x 256 counts are too large
+    and too small).  Every image's gradient against the oracle's, held to the
+    FP32 bounds of the 128^2 test (K <= 2 C n = 3072 here).  After only 6
+    iterations d lambda is a sum of per-iteration dot products that largely
+    cancel, so its own relative error is the FP32 level times that
+    cancellation; it is held, like the whole gradient, through directional
+    derivatives relative to the gradient's norm."""
+    probs = S.diff_problems(count=8, n=512, r=4, iters=6)
+    p0 = probs[0]
+    l, q = p0.center
+    K, H, _, _, _, _ = O.kron_approx64(p0.psf, l, q, p0.bc, p0.r)
+    L = O.lipschitz_power(K, H, p0.v0, 100)
+    u = sf.Unrolled([(dev(p.bobs), dev(K), dev(H), p.lam, L) for p in probs], iters=6, ckpt=3, precision="fp32")
+    Xs = u.forward()
+    dXs = [2.0 * (X - dev(p.x_true)) / X.numel() for X, p in zip(Xs, probs)]
+    dA, dB, dl = u.backward(dXs)
+    u.close()
+    for b, p in enumerate(probs):
+        loss, oK, oH, olam = O.sfista64_grad(K, H, p.bobs, p.lam, L, 6, p.x_true)
+        eX = rel(host(Xs[b]), O.sfista64(K, H, p.bobs, p.lam, L, 6))
+        eA, eB, el = rel(host(dA[b]), oK), rel(host(dB[b]), oH), abs(dl[b] - olam) / abs(olam)
+        say(f"[diff fp32 512^2 image {b}] X {eX:.2e} dA {eA:.2e} dB {eB:.2e} dlam {el:.2e}")
+        assert eX < 1e-5 and eA < 1e-4 and eB < 1e-4
+        gA, gB = host(dA[b]), host(dB[b])
+        rng = np.random.default_rng(200 + b)
+        for _ in range(8):
+            vK, vH, vl = rng.standard_normal(K.shape), rng.standard_normal(H.shape), rng.standard_normal()
+            g = np.sum(gA * vK) + np.sum(gB * vH) + dl[b] * vl
+            o = np.sum(oK * vK) + np.sum(oH * vH) + olam * vl
+            assert abs(g - o) <= 1e-4 * (np.linalg.norm(oK) * np.linalg.norm(vK) +
+                                         np.linalg.norm(oH) * np.linalg.norm(vH) + abs(olam * vl))
