@@ -325,6 +325,10 @@ void orthonormalise(double* Y, int p, int d, hipStream_t s) {
     hipLaunchKernelGGL((cgs2_kernel<16, 2>), dim3(1), dim3(CT), 0, s, Y, p, d);
   else if (p <= 16 && d <= 4 * CT)
     hipLaunchKernelGGL((cgs2_kernel<16, 4>), dim3(1), dim3(CT), 0, s, Y, p, d);
+  else if (p <= 24 && d <= CT)
+    hipLaunchKernelGGL((cgs2_kernel<24, 1>), dim3(1), dim3(CT), 0, s, Y, p, d);
+  else if (p <= 24 && d <= 2 * CT)
+    hipLaunchKernelGGL((cgs2_kernel<24, 2>), dim3(1), dim3(CT), 0, s, Y, p, d);
   else
     hipLaunchKernelGGL(mgs2_kernel, dim3(1), dim3(ST), 0, s, Y, p, d);
 }
