@@ -557,6 +557,9 @@ struct sfista_batch {
   WorkItem* dwork[4][3] = {};       // per product and tile shape: work list
   int nwork[4][3] = {};
   int choice[4] = {0, 0, 0, 0};     // 0 = the mode's big tile, 1 = TileS, 2 = Tile128
+  void* dpow[2] = {};               // power iteration: F2 without Bobs, G2 storing A_s^T A_s V (per problem)
+  std::vector<char> need_L;         // problems whose L the batch estimates
+  int power_steps = 30;
   double* beta = nullptr;           // beta[k] = (t_k - 1) / t_{k+1}, beta[0] = 0
   int* counter = nullptr;           // iterations completed (device)
   hipGraphExec_t gexec = nullptr;
@@ -586,19 +589,22 @@ template <int MODE>
 bool shape_offered(int c) { return c != 2 || !std::is_same<typename BigTile<MODE>::T, Tile128>::value; }
 
 template <int MODE, class T, class Epi>
-hipError_t launch_grouped(sfista_batch* b, int prod) {
+hipError_t launch_grouped(sfista_batch* b, int prod, const void* epis) {
   const int c = tile_shape_index<MODE, T>();
   if (b->nwork[prod][c] == 0) return hipSuccess;
   hipLaunchKernelGGL((gemm_grouped_kernel<MODE, T, Epi>), dim3(b->nwork[prod][c]), dim3(T::THREADS), 0, b->s,
-                     b->dargs[prod], static_cast<const Epi*>(b->depi[prod]), b->dwork[prod][c]);
+                     b->dargs[prod], static_cast<const Epi*>(epis), b->dwork[prod][c]);
   return hipGetLastError();
 }
 
+// Product `prod` of every problem with the epilogue table `epis` (default:
+// the iteration's).
 template <int MODE, class Epi>
-hipError_t launch_product(sfista_batch* b, int prod) {
-  if (b->choice[prod] == 2) return launch_grouped<MODE, Tile128, Epi>(b, prod);
-  return b->choice[prod] ? launch_grouped<MODE, TileS, Epi>(b, prod)
-                         : launch_grouped<MODE, typename BigTile<MODE>::T, Epi>(b, prod);
+hipError_t launch_product(sfista_batch* b, int prod, const void* epis = nullptr) {
+  if (!epis) epis = b->depi[prod];
+  if (b->choice[prod] == 2) return launch_grouped<MODE, Tile128, Epi>(b, prod, epis);
+  return b->choice[prod] ? launch_grouped<MODE, TileS, Epi>(b, prod, epis)
+                         : launch_grouped<MODE, typename BigTile<MODE>::T, Epi>(b, prod, epis);
 }
 
 template <int MODE, int KIND>
@@ -619,6 +625,24 @@ hipError_t batch_iteration(sfista_batch* b) {
   return batch_iteration_k<MODE, ST_F32>(b);
 }
 
+// The G2 epilogues of the iteration: they hold 1 / (L + lambda^2) per problem.
+template <int MODE>
+void fill_update_tables(const sfista_batch* b, std::vector<EpiUpdateSeq<MODE, ST_F64>>& u64,
+                        std::vector<EpiUpdateSeq<MODE, ST_PAIR>>& upr, std::vector<EpiUpdateSeq<MODE, ST_F32>>& u32) {
+  const int cnt = b->count;
+  u64.resize(cnt); upr.resize(cnt); u32.resize(cnt);
+  for (int i = 0; i < cnt; ++i) {
+    const sfista_plan* h = b->plans[i];
+    const double inv = 1.0 / (h->L + h->lam * h->lam);
+    auto fill = [&](auto& u) {
+      u.y[0] = h->Y[0]; u.y[1] = h->Y[1]; u.ldy = h->ldY;
+      u.st[0] = h->st[0]; u.st[1] = h->st[1]; u.n = h->n;
+      u.c1 = h->L * inv; u.c2 = inv; u.nonneg = h->nonneg; u.beta = b->beta; u.counter = b->counter;
+    };
+    fill(u64[i]); fill(upr[i]); fill(u32[i]);
+  }
+}
+
 // Builds the per-product GEMM arguments, epilogues and work lists.
 template <int MODE>
 int batch_build(sfista_batch* b) {
@@ -626,9 +650,9 @@ int batch_build(sfista_batch* b) {
   std::vector<GemmArgs> args[4];
   std::vector<EpiStack<MODE>> e0(cnt), e2(cnt);
   std::vector<EpiResid<MODE>> e1(cnt);
-  std::vector<EpiUpdateSeq<MODE, ST_F64>> u64(cnt);
-  std::vector<EpiUpdateSeq<MODE, ST_PAIR>> upr(cnt);
-  std::vector<EpiUpdateSeq<MODE, ST_F32>> u32(cnt);
+  std::vector<EpiUpdateSeq<MODE, ST_F64>> u64;
+  std::vector<EpiUpdateSeq<MODE, ST_PAIR>> upr;
+  std::vector<EpiUpdateSeq<MODE, ST_F32>> u32;
   using Acc = typename ModeTraits<MODE>::Acc;
   for (int i = 0; i < cnt; ++i) {
     sfista_plan* h = b->plans[i];
@@ -643,14 +667,8 @@ int batch_build(sfista_batch* b) {
     e1[i].out[0] = h->R[0]; e1[i].out[1] = h->R[1]; e1[i].ldo = h->ldR;
     e1[i].bobs_t = static_cast<const Acc*>(h->bobs_t); e1[i].m = m; e1[i].copy = nullptr; e1[i].n = n;
     e2[i].out[0] = h->S[0]; e2[i].out[1] = h->S[1]; e2[i].ldo = h->ldS; e2[i].D = m; e2[i].colblk = n;
-    const double inv = 1.0 / (h->L + h->lam * h->lam);
-    auto fill = [&](auto& u) {
-      u.y[0] = h->Y[0]; u.y[1] = h->Y[1]; u.ldy = h->ldY;
-      u.st[0] = h->st[0]; u.st[1] = h->st[1]; u.n = n;
-      u.c1 = h->L * inv; u.c2 = inv; u.nonneg = h->nonneg; u.beta = b->beta; u.counter = b->counter;
-    };
-    fill(u64[i]); fill(upr[i]); fill(u32[i]);
   }
+  fill_update_tables<MODE>(b, u64, upr, u32);
   auto upload = [&](const void* src, size_t bytes) -> void* {
     void* d = b->arena.alloc_zero(bytes, b->s);
     if (d && hipMemcpyAsync(d, src, bytes, hipMemcpyHostToDevice, b->s) != hipSuccess) return nullptr;
@@ -663,6 +681,18 @@ int batch_build(sfista_batch* b) {
   b->depi[0] = upload(e0.data(), sizeof(e0[0]) * cnt);
   b->depi[1] = upload(e1.data(), sizeof(e1[0]) * cnt);
   b->depi[2] = upload(e2.data(), sizeof(e2[0]) * cnt);
+  {   // the power iteration's tables: F2 without Bobs, G2 storing the product
+    std::vector<EpiResid<MODE>> p1(e1);
+    std::vector<EpiStore<MODE>> p3(cnt);
+    for (int i = 0; i < cnt; ++i) {
+      p1[i].bobs_t = nullptr;
+      p3[i].out = b->plans[i]->aux;
+      p3[i].n = b->plans[i]->n;
+    }
+    b->dpow[0] = upload(p1.data(), sizeof(p1[0]) * cnt);
+    b->dpow[1] = upload(p3.data(), sizeof(p3[0]) * cnt);
+    if (!b->dpow[0] || !b->dpow[1]) return set_error(SFISTA_ERR_NOMEM, "batch allocation failed");
+  }
   if (b->kind == ST_F64) b->depi[3] = upload(u64.data(), sizeof(u64[0]) * cnt);
   else if (b->kind == ST_PAIR) b->depi[3] = upload(upr.data(), sizeof(upr[0]) * cnt);
   else b->depi[3] = upload(u32.data(), sizeof(u32[0]) * cnt);
@@ -689,6 +719,98 @@ int batch_build(sfista_batch* b) {
     }
   }
   return SFISTA_OK;
+}
+
+// ---- batched power iteration: the iteration of run_power for every problem
+// at once, the four products as grouped launches, the per-problem norms as
+// one launch over all problems (same partial/sum structure as sumsq, so each
+// problem's estimate is computed as a lone plan would compute it).
+struct PowerImg {
+  const double* v0;   // start vector
+  double* aux;        // W = A_s^T A_s V, the next V
+  double* red;        // the plan's reduction partials [RED_BLOCKS] + scalars
+  void* Y[2];         // F1 operand planes
+  long ldY;
+  int m, n;
+};
+
+template <int MODE>
+__global__ void pw_planes_kernel(const PowerImg* im, int first) {
+  const PowerImg& d = im[blockIdx.y];
+  const double* x = first ? d.v0 : d.aux;
+  const double scale = 1.0 / sqrt(d.red[RED_BLOCKS]);
+  void* p[2] = {d.Y[0], d.Y[1]};
+  const int n = d.n;
+  const long total = (long)d.m * n;
+  for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < total; e += (long)gridDim.x * blockDim.x) {
+    const long i = e / n, j = e - i * n;
+    store_planes<MODE>(p, op_index<MODE>(i, j, d.ldY), x[e] * scale);
+  }
+}
+
+static __global__ __launch_bounds__(RED_THREADS) void pw_sumsq_partial_kernel(const PowerImg* im, int first) {
+  __shared__ double sh[RED_THREADS / 64];
+  const PowerImg& d = im[blockIdx.y];
+  const double* x = first ? d.v0 : d.aux;
+  const long total = (long)d.m * d.n;
+  double acc = 0.0;
+  for (long e = blockIdx.x * (long)RED_THREADS + threadIdx.x; e < total; e += (long)RED_BLOCKS * RED_THREADS) {
+    const double v = x[e];
+    acc += v * v;
+  }
+  const double t = block_sum(acc, sh);
+  if (threadIdx.x == 0) d.red[blockIdx.x] = t;
+}
+
+static __global__ __launch_bounds__(RED_THREADS) void pw_sumsq_finish_kernel(const PowerImg* im, double* ss) {
+  __shared__ double sh[RED_THREADS / 64];
+  const PowerImg& d = im[blockIdx.y];
+  double acc = 0.0;
+  for (int e = threadIdx.x; e < RED_BLOCKS; e += RED_THREADS) acc += d.red[e];
+  const double t = block_sum(acc, sh);
+  if (threadIdx.x == 0) {
+    d.red[RED_BLOCKS] = t;
+    ss[blockIdx.y] = t;
+  }
+}
+
+// Estimates L for every problem (steps power steps from each plan's start
+// vector) into Lout (host, count entries).
+template <int MODE>
+hipError_t batch_power(sfista_batch* b, const std::vector<const double*>& v0, int steps, std::vector<double>& Lout) {
+  const int cnt = b->count;
+  std::vector<PowerImg> im(cnt);
+  for (int i = 0; i < cnt; ++i) {
+    const sfista_plan* h = b->plans[i];
+    im[i] = PowerImg{v0[i], h->aux, h->red, {h->Y[0], h->Y[1]}, h->ldY, h->m, h->n};
+  }
+  PowerImg* dim = static_cast<PowerImg*>(b->arena.alloc_zero(sizeof(PowerImg) * cnt, b->s));
+  double* ss = static_cast<double*>(b->arena.alloc_zero(sizeof(double) * cnt, b->s));
+  if (!dim || !ss) return hipErrorOutOfMemory;
+  hipError_t e = hipMemcpyAsync(dim, im.data(), sizeof(PowerImg) * cnt, hipMemcpyHostToDevice, b->s);
+  if (e != hipSuccess) return e;
+  auto norms = [&](int first) {
+    hipLaunchKernelGGL(pw_sumsq_partial_kernel, dim3(RED_BLOCKS, cnt), dim3(RED_THREADS), 0, b->s, dim, first);
+    hipLaunchKernelGGL(pw_sumsq_finish_kernel, dim3(1, cnt), dim3(RED_THREADS), 0, b->s, dim, ss);
+  };
+  const dim3 pg(std::max(1, EW_BLOCKS / cnt), cnt);
+  norms(1);
+  hipLaunchKernelGGL(pw_planes_kernel<MODE>, pg, dim3(EW_THREADS), 0, b->s, dim, 1);
+  for (int it = 0; it < steps; ++it) {
+    if ((e = launch_product<MODE, EpiStack<MODE>>(b, 0)) != hipSuccess) return e;
+    if ((e = launch_product<MODE, EpiResid<MODE>>(b, 1, b->dpow[0])) != hipSuccess) return e;
+    if ((e = launch_product<MODE, EpiStack<MODE>>(b, 2)) != hipSuccess) return e;
+    if ((e = launch_product<MODE, EpiStore<MODE>>(b, 3, b->dpow[1])) != hipSuccess) return e;
+    norms(0);
+    if (it + 1 < steps) hipLaunchKernelGGL(pw_planes_kernel<MODE>, pg, dim3(EW_THREADS), 0, b->s, dim, 0);
+  }
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  std::vector<double> h(cnt);
+  if ((e = hipMemcpyAsync(h.data(), ss, sizeof(double) * cnt, hipMemcpyDeviceToHost, b->s)) != hipSuccess) return e;
+  if ((e = hipStreamSynchronize(b->s)) != hipSuccess) return e;
+  Lout.resize(cnt);
+  for (int i = 0; i < cnt; ++i) Lout[i] = sqrt(h[i]);
+  return hipSuccess;
 }
 
 // Times the tile shapes of every product on the batch itself and keeps the
@@ -764,6 +886,48 @@ void tune_cache_store(const std::string& key, const int* choice) {
   f << key << " " << choice[0] << " " << choice[1] << " " << choice[2] << " " << choice[3] << "\n";
 }
 
+// Estimates L for the problems that need it (one batched power iteration),
+// then rebuilds the iteration's G2 epilogues and resets every state.
+template <int MODE>
+int batch_estimate_L(sfista_batch* b) {
+  const int cnt = b->count;
+  bool any = false;
+  for (char c : b->need_L) any = any || c;
+  if (!any) return SFISTA_OK;
+  std::vector<const double*> v0(cnt);
+  for (int i = 0; i < cnt; ++i) {
+    sfista_plan* h = b->plans[i];
+    // the fixed internal start of a lone plan (same hash, same seed)
+    if (!h->v0buf && !(h->v0buf = static_cast<double*>(h->mem->alloc_zero((size_t)h->m * h->n * 8, b->s))))
+      return set_error(SFISTA_ERR_NOMEM, "batch allocation failed");
+    hipLaunchKernelGGL(hash_fill_kernel, dim3(EW_BLOCKS), dim3(EW_THREADS), 0, b->s, h->v0buf, (long)h->m * h->n,
+                       0x5f15a7ull);
+    v0[i] = h->v0buf;
+  }
+  std::vector<double> L;
+  hipError_t e = batch_power<MODE>(b, v0, b->power_steps, L);
+  if (e != hipSuccess) return hip_fail(e, "batch power iteration");
+  for (int i = 0; i < cnt; ++i) {
+    if (!b->need_L[i]) continue;
+    if (!isfinite(L[i]) || !(L[i] > 0.0)) return set_error(SFISTA_ERR_NONFINITE, "problem %d: Lipschitz estimate is %g", i, L[i]);
+    b->plans[i]->L = L[i];
+  }
+  std::vector<EpiUpdateSeq<MODE, ST_F64>> u64;
+  std::vector<EpiUpdateSeq<MODE, ST_PAIR>> upr;
+  std::vector<EpiUpdateSeq<MODE, ST_F32>> u32;
+  fill_update_tables<MODE>(b, u64, upr, u32);
+  if (b->kind == ST_F64) e = hipMemcpyAsync(b->depi[3], u64.data(), sizeof(u64[0]) * cnt, hipMemcpyHostToDevice, b->s);
+  else if (b->kind == ST_PAIR) e = hipMemcpyAsync(b->depi[3], upr.data(), sizeof(upr[0]) * cnt, hipMemcpyHostToDevice, b->s);
+  else e = hipMemcpyAsync(b->depi[3], u32.data(), sizeof(u32[0]) * cnt, hipMemcpyHostToDevice, b->s);
+  for (sfista_plan* h : b->plans)
+    hipLaunchKernelGGL(init_state_kernel<MODE>, dim3(EW_BLOCKS), dim3(EW_THREADS), 0, b->s, nullptr, h->st[0],
+                       h->st[1], h->kind, h->Y[0], h->Y[1], h->ldY, h->m, h->n);
+  if (e == hipSuccess) e = hipGetLastError();
+  if (e == hipSuccess) e = hipStreamSynchronize(b->s);   // the host tables die here
+  if (e != hipSuccess) return hip_fail(e, "batch setup");
+  return SFISTA_OK;
+}
+
 template <int MODE>
 int batch_setup_mode(sfista_batch* b) {
   int rc = batch_build<MODE>(b);
@@ -777,6 +941,7 @@ int batch_setup_mode(sfista_batch* b) {
     b->choice[q] = b->nwork[q][0] >= 2 * slots ? 0 : (shape_offered<MODE>(2) && b->nwork[q][2] >= 2 * cus) ? 2 : 1;
   for (int q = 0; q < 4; ++q)
     if (!shape_offered<MODE>(b->choice[q])) b->choice[q] = 1;
+  if ((rc = batch_estimate_L<MODE>(b)) != SFISTA_OK) return rc;
   if (b->flags & SFISTA_BATCH_AUTOTUNE) {
     const std::string key = batch_key(b);
     if (!tune_cache_lookup(key, b->choice)) {
@@ -847,10 +1012,14 @@ int sfista_batch_setup(const sfista_batch_item* items, int count, const sfista_p
     delete b;
     return hip_fail(e, "batch stream");
   }
+  b->power_steps = common->power_iters > 0 ? common->power_iters : 30;
   for (int i = 0; i < count; ++i) {
     sfista_params p = *common;
     p.lambda = items[i].lambda;
-    p.L = items[i].L;
+    // L <= 0: estimated below for all such problems at once; the plan holds
+    // a placeholder until then
+    b->need_L.push_back(items[i].L > 0.0 ? 0 : 1);
+    p.L = items[i].L > 0.0 ? items[i].L : 1.0;
     sfista_handle h = nullptr;
     const int rc =
         plan_create(items[i].Bobs, items[i].m, items[i].n, items[i].A, items[i].B, items[i].r, &p, b->s, &b->arena, &h);
