@@ -42,10 +42,12 @@ def _rand_factors(m, n, r, seed):
 
 
 @pytest.mark.parametrize("mode", MODES)
-@pytest.mark.parametrize("m,n,r", [(64, 64, 1), (200, 136, 3), (257, 130, 2)])
+@pytest.mark.parametrize("m,n,r", [(64, 64, 1), (200, 136, 3), (257, 130, 2),
+                                   (1, 1, 1), (1, 37, 1), (45, 1, 1), (7, 7, 7)])
 def test_operator_matches_oracle_within_rounding_bound(sf, mode, m, n, r):
     """A_s X and A_s^T A_s X with the plan's four GEMMs (ragged sizes, several
-    tiles, rectangular images) against FP64, element by element."""
+    tiles, rectangular images; a single pixel, a single row, a single column
+    and full rank r = m = n) against FP64, element by element."""
     say(f"[apply] mode={mode} m={m} n={n} r={r}")
     A, B, X = _rand_factors(m, n, r, seed=m * 1000 + n + r)
     s = sf.Solver(dev(np.zeros((m, n))), dev(A), dev(B), lam=0.1, L=1.0, precision=mode)
@@ -328,3 +330,45 @@ def test_kernel_times_report_each_launch(sf):
         assert cnt[4 + g] in (0, 10)
         assert (ms[4 + g] > 0.0) == (cnt[4 + g] == 10)
     s.close()
+
+
+@pytest.mark.parametrize("mode", ["fp64", "bf16x3"])
+def test_lambda_zero_matches_oracle(sf, mode):
+    """lambda = 0 (no Tikhonov term: FISTA on the least-squares data term)."""
+    p = S.config(1, n=48)
+    K, H = _oracle_setup(p)
+    L = O.lipschitz_power(K, H, p.v0, 300)
+    s = sf.Solver(dev(p.bobs), dev(K), dev(H), lam=0.0, L=L, precision=mode)
+    X, rep = s.solve(60)
+    ref = O.sfista64(K, H, p.bobs, 0.0, L, 60)
+    e = rel(host(X), ref)
+    say(f"[lambda 0] {mode}: rel err {e:.2e}")
+    assert e < (1e-12 if mode == "fp64" else 1e-5)
+    assert math.isclose(rep["phi_s"], O.phi_s(K, H, p.bobs, ref, 0.0), rel_tol=1e-5)
+    s.close()
+
+
+@pytest.mark.parametrize("mode", MODES)
+def test_zero_observation_keeps_zero_iterates(sf, mode):
+    """Bobs = 0 and X_0 = 0: every product and update is exactly zero, so the
+    iterates stay exactly 0 in every mode, and so do phi_s and ||R||."""
+    p = S.config(1, n=40)
+    K, H = _oracle_setup(p)
+    s = sf.Solver(dev(np.zeros_like(p.bobs)), dev(K), dev(H), lam=p.lam, L=1.0, precision=mode)
+    X, rep = s.solve(15)
+    assert not np.any(host(X))
+    assert rep["phi_s"] == 0.0 and rep["resid_norm"] == 0.0
+    s.close()
+
+
+def test_zero_factors_are_rejected(sf):
+    """A_s = 0: the power estimate of L is 0, which setup reports as a
+    non-finite / non-positive Lipschitz estimate (GEMM and FFT forms)."""
+    m, n, r = 24, 20, 2
+    z = lambda *sh: dev(np.zeros(sh))
+    with pytest.raises(sf.SfistaError) as ei:
+        sf.Solver(z(m, n), z(r, n, n), z(r, m, m), lam=0.1, precision="fp64", power_iters=5)
+    assert ei.value.code == sf.SFISTA_ERR_NONFINITE
+    with pytest.raises(sf.SfistaError) as ei:
+        sf.FftSolver(z(m, n), z(r, m), z(r, n), m // 2, n // 2, 1, lam=0.1, power_iters=5)
+    assert ei.value.code == sf.SFISTA_ERR_NONFINITE
