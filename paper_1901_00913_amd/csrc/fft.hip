@@ -24,10 +24,11 @@
 // Twiddles come from a table, three reads per pass, the other powers by
 // products.  Transforms are FP32; the iterates are FP64.
 //
-// One iteration is four line passes over the image (m x n, row-major):
+// One iteration is four line passes over the image (m x n, row-major), in
+// three kernels (F2 and G1 run along the same lines and share one):
 //   F1  T_k = Y A_k^T      rows of Y, one transform in, r out (stored T_k^T)
-//   F2  R = sum_k B_k T_k - Bobs   rows of T_k^T, r in, one out (R^T)
-//   G1  S_k = B_k^T R      rows of R^T, one in, r out (S_k^T)
+//   F2  R = sum_k B_k T_k - Bobs   rows of T_k^T, r in, one out
+//   G1  S_k = B_k^T R      the same lines, one in, r out (S_k^T)
 //   G2  G = sum_k S_k A_k  rows of S_k (columns of S_k^T), r in, one out,
 //       fused with Steps 1 and 3 (X_k and Y_{k+1}).
 // C ABI declared in include/sfista.h.
@@ -371,14 +372,12 @@ struct EpiUpdate {       // Steps 1 and 3 of Algorithm 2 on row L
   long ld;
   double c1, c2, beta;   // c1 = L / (L + lambda^2), c2 = 1 / (L + lambda^2)
   int nonneg;
-  __device__ double put(int L, int e, float g) const {   // returns Y_{k+1} at (L, e)
+  __device__ void put(int L, int e, float g) const {
     const long i = (long)L * ld + e;
     double x = c1 * y[i] - c2 * (double)g;
     if (nonneg) x = x > 0.0 ? x : 0.0;
     xout[i] = x;
-    const double yn = x + beta * (x - xprev[i]);
-    y[i] = yn;
-    return yn;
+    y[i] = x + beta * (x - xprev[i]);
   }
 };
 
@@ -581,83 +580,6 @@ __global__ __launch_bounds__(fft_threads(N)) void column_pass_kernel(LinesF32<fa
   }
 }
 
-// Row pass of an iteration, G2 with Steps 1 and 3 on a pair of rows, then
-// (with_f1) F1 of the next iteration on the same rows: the new Y_{k+1} rows
-// are staged in LDS (rounded to FP32, as F1 reads them) and the extended
-// line is gathered from there, so F1 needs no read of Y from memory.
-template <int N>
-__global__ __launch_bounds__(fft_threads(N)) void row_pass_kernel(LinesF32<true> in, EpiUpdate epi,
-                                                                OutTransposed out, const float2* __restrict__ spec,
-                                                                const float2* __restrict__ tw, int M, int nlines,
-                                                                int c0, int refl, int r, int with_f1) {
-  constexpr int FT = fft_threads(N);
-  constexpr int PER = N / FT;
-  __shared__ float2 buf[N];
-  const int a = 2 * line_group();
-  if (a >= nlines) return;
-  const bool bv = a + 1 < nlines;
-  float2 acc[PER];
-#pragma unroll
-  for (int u = 0; u < PER; ++u) acc[u] = make_float2(0.f, 0.f);
-  for (int k = 0; k < r; ++k) {
-    float2 x[PER];
-    fetch_pair<N, true>(x, in, k, a, bv, M, c0, refl, 1.0);
-    fft<N, true, true>(x, buf, tw);
-    const float2* sk = spec + (long)k * N;
-#pragma unroll
-    for (int u = 0; u < PER; ++u) acc[u] = cadd(acc[u], cmulconj(x[u], sk[(int)threadIdx.x + u * FT]));
-  }
-#pragma unroll
-  for (int u = 0; u < PER; ++u) acc[u] = make_float2(acc[u].x, -acc[u].y);
-  fft<N, true, false>(acc, buf, tw);
-  const float inv = 1.0f / (float)N;
-  float2 ynew[(N / 2 + FT - 1) / FT];   // entries e = t + v FT < M <= N / 2
-#pragma unroll
-  for (int v = 0; v < (N / 2 + FT - 1) / FT; ++v) {
-    const int e = (int)threadIdx.x + v * FT;
-    ynew[v] = make_float2(0.f, 0.f);
-    if (e < M) {
-      const float2 w = fold_at(buf, e, M, c0, refl);
-      ynew[v].x = (float)epi.put(a, e, w.x * inv);
-      if (bv) ynew[v].y = (float)epi.put(a + 1, e, -w.y * inv);
-    }
-  }
-  if (!with_f1) return;
-  __syncthreads();   // every fold read of buf is done
-#pragma unroll
-  for (int v = 0; v < (N / 2 + FT - 1) / FT; ++v) {
-    const int e = (int)threadIdx.x + v * FT;
-    if (e < M) buf[e] = ynew[v];
-  }
-  __syncthreads();
-  float2 z[PER];
-#pragma unroll
-  for (int u = 0; u < PER; ++u) {   // the extension w of the two rows, as F1 loads it
-    const int p = (int)threadIdx.x + u * FT;
-    z[u] = make_float2(0.f, 0.f);
-    if (p < 2 * M - 1) {
-      const int src = ext_src(p + c0 - (M - 1), M, refl);
-      if (src >= 0) z[u] = buf[src];
-    }
-  }
-  fft<N, true, true>(z, buf, tw);
-  for (int k = 0; k < r; ++k) {
-    const float2* sk = spec + (long)k * N;
-    float2 x[PER];
-#pragma unroll
-    for (int u = 0; u < PER; ++u) {
-      const float2 q = cmul(z[u], sk[(int)threadIdx.x + u * FT]);
-      x[u] = make_float2(q.x, -q.y);
-    }
-    fft<N, true, true>(x, buf, tw);
-#pragma unroll
-    for (int u = 0; u < PER; ++u) {
-      const int p = (int)threadIdx.x + u * FT;
-      if (p >= M - 1 && p < 2 * M - 1) out.put2(k, a, bv, p - (M - 1), x[u].x * inv, -x[u].y * inv);
-    }
-  }
-}
-
 // Spectrum of generator k (length M, zero-padded to N): spec[k N + e].
 template <int N>
 __global__ __launch_bounds__(fft_threads(N)) void spectrum_kernel(const double* gen, int M, float2* spec,
@@ -724,7 +646,6 @@ struct sfista_fft {
   hipStream_t s = nullptr;
   long iter = 0;          // iterations completed (k)
   double tk = 1.0;        // t_{k+1}
-  bool t_valid = false;   // T_k (Tt) holds F1 of the current Y
   int Nm = 0, Nn = 0;     // transform sizes along columns (m) and rows (n)
   long ldt = 0;           // leading dimension of the transposed arrays (>= m, even)
   float2 *twm = nullptr, *twn = nullptr;      // W_N^t tables
@@ -742,7 +663,6 @@ namespace {
 
 // The four line passes.  `in` is the F1 input (FP64 rows, optionally scaled).
 hipError_t pass_f1(sfista_fft* h, const double* x, const double* ss) {
-  h->t_valid = x == h->Y && !ss;
   return with_size(h->Nn, [&]<int N>() -> hipError_t {
     hipLaunchKernelGGL((fan_out_kernel<N, false, RowsF64, OutTransposed>), dim3((h->m + 1) / 2),
                        dim3(fft_threads(N)), 0, h->s, RowsF64{x, h->n, ss},
@@ -805,31 +725,16 @@ hipError_t pass_columns(sfista_fft* h) {
   });
 }
 
-// G2 with Steps 1 and 3, and (with_f1) F1 of the next iteration, in one
-// pass over the row pairs.
-hipError_t pass_rows(sfista_fft* h, const EpiUpdate& epi, bool with_f1) {
-  h->t_valid = with_f1;
-  return with_size(h->Nn, [&]<int N>() -> hipError_t {
-    hipLaunchKernelGGL((row_pass_kernel<N>), dim3((h->m + 1) / 2), dim3(fft_threads(N)), 0, h->s,
-                       LinesF32<true>{h->St, 1, h->ldt, (long)h->n * h->ldt, nullptr}, epi,
-                       OutTransposed{h->Tt, h->ldt, (long)h->n * h->ldt}, h->specK, h->twn, h->n, h->m, h->q,
-                       h->refl, h->r, with_f1 ? 1 : 0);
-    return hipGetLastError();
-  });
-}
-
-// One iteration; `next`: another iteration follows in this call, so the
-// row pass also computes its F1.
-hipError_t run_iteration(sfista_fft* h, bool next) {
+hipError_t run_iteration(sfista_fft* h) {
   hipError_t e;
   const long k = h->iter + 1;
   const double tn = (1.0 + sqrt(1.0 + 4.0 * h->tk * h->tk)) / 2.0;   // t_{k+1}
   const double beta = (h->tk - 1.0) / tn;                            // Step 3
   const double den = h->L + h->lam * h->lam;
-  if (!h->t_valid && (e = pass_f1(h, h->Y, nullptr)) != hipSuccess) return e;
+  if ((e = pass_f1(h, h->Y, nullptr)) != hipSuccess) return e;
   if ((e = pass_columns(h)) != hipSuccess) return e;
-  if ((e = pass_rows(h, EpiUpdate{h->X[(k - 1) & 1], h->X[k & 1], h->Y, h->n, h->L / den, 1.0 / den, beta,
-                                  h->nonneg}, next)) != hipSuccess)
+  if ((e = pass_g2(h, EpiUpdate{h->X[(k - 1) & 1], h->X[k & 1], h->Y, h->n, h->L / den, 1.0 / den, beta,
+                                h->nonneg})) != hipSuccess)
     return e;
   h->tk = tn;
   h->iter = k;
@@ -967,7 +872,7 @@ int sfista_fft_step(sfista_fft_handle h, int iters) {
   if (!h) return set_error(SFISTA_ERR_ARG, "NULL handle");
   if (iters < 0) return set_error(SFISTA_ERR_ARG, "iters must be >= 0");
   for (int i = 0; i < iters; ++i) {
-    const hipError_t e = run_iteration(h, i + 1 < iters);
+    const hipError_t e = run_iteration(h);
     if (e != hipSuccess) return hip_fail(e, "sfista_fft_step");
   }
   return SFISTA_OK;
@@ -989,7 +894,7 @@ int sfista_fft_solve(sfista_fft_handle h, int max_iters, double tol, double* X_o
   while (done < max_iters && e == hipSuccess) {
     int chunk = max_iters - done;
     if (tol > 0.0 && chunk > 10) chunk = 10;
-    for (int i = 0; i < chunk && e == hipSuccess; ++i) e = run_iteration(h, done + i + 1 < max_iters);
+    for (int i = 0; i < chunk && e == hipSuccess; ++i) e = run_iteration(h);
     if (e != hipSuccess) break;
     done += chunk;
     if (tol > 0.0 && h->iter >= 1) {
