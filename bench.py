@@ -310,7 +310,10 @@ def run_fft(args, dev, steps, warmup):
     Nm, Nn = nfft(m), nfft(n)
     fl = lambda N, lines: (r + 1) * ((lines + 1) // 2) * 5.0 * N * math.log2(N)
     flops_it = 2 * fl(Nn, m) + 2 * fl(Nm, n)
-    bytes_it = m * n * (52 + 16 * r)   # algorithmic HBM bytes of the four passes
+    # algorithmic HBM bytes per iteration: F1 reads Y (8) and writes r T_k (4 r); the column pass reads
+    # r T_k (4 r) and Bobs^T (4) and writes r S_k (4 r); G2 reads r S_k (4 r), Y and X_{k-1} (16) and
+    # writes X_k and Y_{k+1} (16), per pixel
+    bytes_it = m * n * (44 + 16 * r)
     log(f"[fft] {steps} steps in {elapsed:.3f} s -> {value:.1f} it/s; iterations only {iters / iter_s:.1f} it/s")
     summary = {"its_per_s": value, "iteration_only_its": iters / iter_s, "ms_per_step": elapsed / steps * 1e3,
                "fft_tflops": flops_it / (iter_s / iters) / 1e12,
