@@ -199,3 +199,30 @@ def test_config3_fullsize_first_iterations(sf):
     say(f"[fft cfg3] 5 iterations rel err {e:.3e}")
     assert e < 1e-5
     s.close()
+
+
+def test_tolerance_stop(sf):
+    """solve(tol): the FFT form stops at the first multiple of 10 iterations
+    where ||X_k - X_{k-1}|| <= tol ||X_k||.  The iterates carry FP32 transform
+    rounding (about 3e-7 of ||X||), so tol = 1e-4 keeps the step norms far
+    above it, and the oracle's trajectory is checked with a 5% margin: the
+    criterion holds at the stopping iteration and failed 10 iterations
+    earlier."""
+    p = S.config(1, n=40)
+    l, q = p.center
+    K, H, _, _, oh, ok = O.kron_approx64(p.psf, l, q, p.bc, p.r)
+    L = O.lipschitz_power(K, H, p.v0, 200)
+    tol = 1e-4
+    s = sf.FftSolver(dev(p.bobs), dev(oh), dev(ok), l, q, p.bc, lam=0.1, L=L)
+    X, rep = s.solve(5000, tol=tol)
+    k = rep["iters"]
+    s.close()
+    assert 10 <= k < 5000 and k % 10 == 0
+    hist = []
+    O.sfista64(K, H, p.bobs, 0.1, L, k, history=hist)
+    step = lambda j: np.linalg.norm(hist[j] - hist[j - 1]) / np.linalg.norm(hist[j])
+    say(f"[fft tol] stopped at {k}: oracle step {step(-1):.3e}, 10 earlier {step(-11):.3e}")
+    assert step(-1) <= tol * 1.05
+    if k > 10:
+        assert step(-11) > tol * 0.95
+    assert rel(host(X), hist[-1]) < 1e-5
