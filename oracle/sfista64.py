@@ -424,6 +424,38 @@ def lipschitz_power(K, H, V0, steps: int) -> float:
     return est
 
 
+def lipschitz_lanczos(K, H, V0, steps: int) -> float:
+    """Lanczos estimate of ``lambda_max(A_s^T A_s)`` (Section 4 takes L from
+    a Lanczos estimate of the operator norm; on ``A_s^T A_s`` the symmetric
+    Lanczos process is, in exact arithmetic, the Golub-Kahan
+    bidiagonalisation of ``A_s``).  From ``q_1 = V0 / ||V0||`` and
+    ``q_0 = 0``, ``beta_0 = 0``, step ``j`` forms ``w = A_s^T A_s q_j``,
+    ``alpha_j = <q_j, w>``, ``w -= alpha_j q_j + beta_{j-1} q_{j-1}``,
+    ``beta_j = ||w||`` and ``q_{j+1} = w / beta_j``.  The estimate is the
+    largest eigenvalue of the symmetric tridiagonal matrix with diagonal
+    ``alpha_1..alpha_k`` and off-diagonal ``beta_1..beta_{k-1}``.  No
+    reorthogonalisation.  The process stops early when ``beta_j`` vanishes
+    (the Krylov space is invariant, and its Ritz values are exact)."""
+    q = np.asarray(V0, dtype=np.float64)
+    q = q / np.linalg.norm(q)
+    q_prev = np.zeros_like(q)
+    beta_prev = 0.0
+    alpha, beta = [], []
+    for _ in range(steps):
+        w = apply_AsT(K, H, apply_As(K, H, q))
+        a = float(np.sum(q * w))
+        w = w - a * q - beta_prev * q_prev
+        b = float(np.linalg.norm(w))
+        alpha.append(a)
+        if b == 0.0:
+            break
+        beta.append(b)
+        q_prev, q, beta_prev = q, w / b, b
+    k = len(alpha)
+    T = np.diag(alpha) + np.diag(beta[:k - 1], 1) + np.diag(beta[:k - 1], -1)
+    return float(np.linalg.eigvalsh(T)[-1])
+
+
 def closed_form(A, b, lam):
     """Minimiser of the (unconstrained) vector model: the solution of the
     optimality condition ``A^T(A x - b) + lam^2 x = 0`` (Theorem 4's proof)."""

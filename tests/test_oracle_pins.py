@@ -218,6 +218,86 @@ def test_power_iteration_matches_eigensolver():
     assert math.isclose(O.lipschitz_power(K, H, v0, 400), O.lipschitz_dense(As), rel_tol=1e-10)
 
 
+def _krylov_ritz_max(M, v0, k):
+    """Rayleigh-Ritz on the Krylov space span{v0, M v0, ..., M^(k-1) v0}
+    from its definition: an orthonormal basis by QR of the (column-scaled)
+    Krylov matrix, then the largest eigenvalue of Q^T M Q."""
+    cols, v = [], v0 / np.linalg.norm(v0)
+    for _ in range(k):
+        cols.append(v)
+        v = M @ v
+        v = v / np.linalg.norm(v)
+    Q, _ = np.linalg.qr(np.stack(cols, axis=1))
+    return float(np.linalg.eigvalsh(Q.T @ M @ Q)[-1])
+
+
+@pytest.mark.parametrize("k", [1, 2, 3, 4, 5])
+def test_lanczos_equals_rayleigh_ritz_on_krylov_space(k):
+    """k Lanczos steps give the largest Ritz value of the k-dimensional
+    Krylov space (the definition of the Lanczos estimate), built here with
+    an explicit basis and a dense A_s^T A_s.  k = 1 is the Rayleigh
+    quotient of v0."""
+    x, psf, K, H, As, bobs, lam = _small_problem()
+    M = As.T @ As
+    v0 = S.power_start(*bobs.shape, seed=11)
+    ref = _krylov_ritz_max(M, O.vec(v0), k)
+    if k == 1:
+        u = O.vec(v0)
+        assert math.isclose(ref, u @ M @ u / (u @ u), rel_tol=1e-13)
+    assert math.isclose(O.lipschitz_lanczos(K, H, v0, k), ref, rel_tol=1e-11)
+
+
+def test_lanczos_converges_to_the_eigenvalue_and_rises_monotonically():
+    """Interlacing: the largest Ritz value never falls as the Krylov space
+    grows and never exceeds lambda_max(A_s^T A_s) (a dense eigensolver);
+    with as many steps as unknowns it reaches it."""
+    x, psf, K, H, As, bobs, lam = _small_problem(m=6, n=5, s=2)
+    v0 = S.power_start(*bobs.shape, seed=3)
+    lmax = O.lipschitz_dense(As)
+    prev = -np.inf
+    for k in range(1, 13):
+        est = O.lipschitz_lanczos(K, H, v0, k)
+        assert est >= prev - 1e-13 * lmax and est <= lmax * (1 + 1e-12)
+        prev = est
+    assert math.isclose(O.lipschitz_lanczos(K, H, v0, 30), lmax, rel_tol=1e-10)
+
+
+def test_lanczos_rank1_closed_form():
+    """r = 1: A_s^T A_s = (K^T K) (x) (H^T H), whose largest eigenvalue is
+    ||K||_2^2 ||H||_2^2 (two library SVDs)."""
+    rng = np.random.default_rng(5)
+    m, n = 20, 30
+    K = rng.standard_normal((1, n, n)) / math.sqrt(n)
+    H = rng.standard_normal((1, m, m)) / math.sqrt(m)
+    ref = (np.linalg.norm(K[0], 2) * np.linalg.norm(H[0], 2)) ** 2
+    assert math.isclose(O.lipschitz_lanczos(K, H, rng.standard_normal((m, n)), 120), ref, rel_tol=1e-9)
+
+
+def test_lanczos_stops_on_an_invariant_space():
+    """Scaled identities: every start vector is an eigenvector of
+    A_s^T A_s = (a b)^2 I, so the first step's residual vanishes and the
+    estimate is (a b)^2, however many steps are asked for (a step past the
+    vanishing residual would divide by zero).  The constant start and these
+    scales keep every operation exact in binary floating point."""
+    m, n, a, b = 4, 4, 1.5, 0.5
+    K = (a * np.eye(n))[None]
+    H = (b * np.eye(m))[None]
+    v0 = np.ones((m, n))
+    assert O.lipschitz_lanczos(K, H, v0, 10) == (a * b) ** 2
+
+
+def test_lanczos_beats_power_on_a_blur():
+    """On a reflexive Gaussian blur (slowly separating top eigenvalues) 10
+    Lanczos steps land closer to lambda_max than 30 power steps."""
+    x, psf, K, H, As, bobs, lam = _small_problem(m=24, n=20, s=3)
+    v0 = S.power_start(*bobs.shape, seed=11)
+    lmax = O.lipschitz_dense(As)
+    lz = O.lipschitz_lanczos(K, H, v0, 10)
+    pw = O.lipschitz_power(K, H, v0, 30)
+    assert pw <= lmax * (1 + 1e-12) and lz <= lmax * (1 + 1e-12)
+    assert lmax - lz < lmax - pw
+
+
 def test_theorem4_error_falls_with_rank():
     """Theorem 4: the gap |Phi(x_k) - Phi(x*)| is bounded by a decaying FISTA
     term plus c0 eps_s; eps_s and the plateau of the gap fall as s grows."""
