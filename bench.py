@@ -6,7 +6,8 @@ rotated Gaussian PSF sigma = (4, 12), theta = 30 deg, r = 5 Kronecker terms,
 1% noise, lambda = 0.02, 300 iterations, split-BF16x3 GEMMs with
 float-float iterate state).  One timed step is the whole path on one
 synthetic image already resident in HBM: the Kronecker approximation
-(kron_approx), the plan setup with the power iteration for L, 300
+(kron_approx), the plan setup with the estimate of L (12 Lanczos steps, as
+Section 4 estimates it; --l-estimate power for 30 power steps), 300
 iterations of Algorithm 2 and the FP64 report.  `value` is iterations per
 second of whole steps.
 
@@ -264,10 +265,15 @@ def run_paper(args, dev, steps, warmup):
     return {"line": line, "summary": rows}
 
 
+def l_steps(args) -> int:
+    """Steps of the estimate of L that the library runs for these options."""
+    return args.l_steps or (12 if args.l_estimate == "lanczos" else 30)
+
+
 def run_fft(args, dev, steps, warmup):
     """Structured-FFT form on the precision workload (2048^2, r = 5,
     reflexive, 300 iterations): a step runs kron_generators, the plan setup
-    with the power estimate of L and the iterations, as the default line does
+    with the estimate of L and the iterations, as the default line does
     with dense factors.  Transforms are FP32, iterates FP64."""
     import torch
 
@@ -284,7 +290,8 @@ def run_fft(args, dev, steps, warmup):
 
     def step():
         h, k, _, eps = sfista.kron_generators(P, l, q, p.bc, r)
-        s = sfista.FftSolver(Bobs, h, k, l, q, p.bc, lam=p.lam, power_iters=args.power_iters, v0=v0)
+        s = sfista.FftSolver(Bobs, h, k, l, q, p.bc, lam=p.lam, power_iters=args.l_steps, v0=v0,
+                             l_estimate=args.l_estimate)
         _, rep = s.solve(iters, want_x=False)
         L = s.L
         s.close()
@@ -343,7 +350,9 @@ def main():
     ap.add_argument("--n", type=int, default=2048, help="image size (the workload is 2048)")
     ap.add_argument("--iters", type=int, default=300)
     ap.add_argument("--precision", default="bf16x3", choices=sorted(PEAK_TFLOPS))
-    ap.add_argument("--power-iters", type=int, default=30)
+    ap.add_argument("--l-estimate", default="lanczos", choices=["lanczos", "power"],
+                    help="estimate of L in each step (Section 4 uses Lanczos)")
+    ap.add_argument("--l-steps", type=int, default=0, help="steps of that estimate (0: 12 Lanczos, 30 power)")
     ap.add_argument("--cpu-iters", type=int, default=3, help="oracle iterations timed for cpu_baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp32-compare", action="store_true")
@@ -352,7 +361,7 @@ def main():
                     help="precision-2048: one 2048^2 image, r = 5 (default); batch64: 64 uneven images "
                          "in grouped launches replayed from a HIP graph; diff8: gradient of 50 unrolled "
                          "iterations for 8 images at 512^2, r = 4; paper256: the paper-shaped sweep "
-                         "(256^2, reflexive, 1% noise, defocus and motion blur, s = 1..5, 50 iterations); "
+                         "(256^2, reflexive, 1%% noise, defocus and motion blur, s = 1..5, 50 iterations); "
                          "fft2048: the default workload in the structured-FFT form")
     ap.add_argument("--no-batch", action="store_true", help="skip the batch64 summary in the default line")
     ap.add_argument("--no-diff", action="store_true", help="skip the diff8 summary in the default line")
@@ -397,7 +406,8 @@ def main():
 
     def step(timing):
         A, B, sigma, eps = sfista.kron_approx(P, l, q, bc, r)
-        s = sfista.Solver(Bobs, A, B, lam=lam, precision=args.precision, power_iters=args.power_iters, v0=v0)
+        s = sfista.Solver(Bobs, A, B, lam=lam, precision=args.precision, power_iters=args.l_steps, v0=v0,
+                          l_estimate=args.l_estimate)
         if timing:
             s.set_timing(True)
         _, rep = s.solve(iters, want_x=False)
@@ -519,7 +529,7 @@ def main():
         "scaling": "weak", "vs_baseline": None, "dtype": args.precision, "data": "synthetic",
         "config": {"workload": f"sfista-{m}x{n}-r{r}-reflexive-{iters}it", "image": [m, n], "rank": r,
                    "iters": iters, "precision": args.precision, "lambda": lam,
-                   "power_iters": args.power_iters, "parallelism": "single-gpu"},
+                   "l_estimate": args.l_estimate, "l_steps": l_steps(args), "parallelism": "single-gpu"},
         "roofline": {"bound": "mfma", "kernel": dom, "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
                      "frac": achieved / peak, "traffic": measured_traffic(dom, args.precision, m, n, r),
                      "flops_basis": "executed MFMA flops per launch (bf16x3: 3 bf16 products of 2*M*N*K)",

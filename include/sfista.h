@@ -60,20 +60,41 @@ typedef enum {
     SFISTA_FP64 = 0, SFISTA_FP32 = 1, SFISTA_BF16 = 2, SFISTA_FP16 = 3, SFISTA_BF16X3 = 4
 } sfista_precision;
 
+/* Estimate of L = lambda_max(A_s^T A_s) when the caller gives none.
+ *   SFISTA_L_POWER    power iteration: V <- A_s^T A_s V / ||V||, L = ||A_s^T A_s V||
+ *                     for the last unit V (converges from below).
+ *   SFISTA_L_LANCZOS  symmetric Lanczos on A_s^T A_s without reorthogonalisation
+ *                     (Section 4 takes L from a Lanczos estimate of the norm): L is
+ *                     the largest eigenvalue of the tridiagonal matrix of the
+ *                     recurrence (bisection on the host), cut at the first
+ *                     vanishing off-diagonal; also from below, and on blur
+ *                     operators far closer than the same number of power steps
+ *                     (a Krylov space's best Rayleigh quotient).
+ * Both start from v0 (or the internal start) and run in the plan's precision,
+ * with FP64 vectors, inner products and norms. */
+typedef enum {
+    SFISTA_L_POWER = 0,
+    SFISTA_L_LANCZOS = 1
+} sfista_l_estimate;
+
 typedef struct {
     double lambda;       /* Tikhonov parameter, finite and >= 0 (Section 1) */
     double L;            /* Lipschitz constant of the data term, lambda_max(A_s^T A_s)
                             (Algorithm 2's input); <= 0 asks the library to estimate it
-                            by power iteration */
+                            (see l_estimate) */
     int precision;       /* sfista_precision */
     int nonneg;          /* 1: project every iterate on X >= 0 (the constraint of
                             Section 1); 0: Algorithm 2 as printed */
-    int power_iters;     /* power-iteration steps when L <= 0; 0 selects 30 */
+    int power_iters;     /* steps of the estimate of L when L <= 0; 0 selects 30 power
+                            steps or 12 Lanczos steps */
     int pair_state;      /* non-FP64 modes: 1 keeps X in float-float (hi + lo fp32),
                             0 in plain fp32; ignored in FP64 mode */
     const double* x0;    /* (device) m x n initial point X_0, or NULL for X_0 = 0 */
-    const double* v0;    /* (device) m x n start of the power iteration, or NULL for a
+    const double* v0;    /* (device) m x n start of the estimate of L, or NULL for a
                             fixed internal start */
+    int l_estimate;      /* sfista_l_estimate: how L is estimated when L <= 0 (the
+                            single-image GEMM and FFT forms; the batched and
+                            differentiable forms take SFISTA_L_POWER only) */
 } sfista_params;
 
 typedef struct {

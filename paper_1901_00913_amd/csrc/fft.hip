@@ -655,6 +655,8 @@ struct sfista_fft {
   double* aux = nullptr;                      // m x n FP64 scratch (power iterate, residual)
   double* red = nullptr;                      // reduction partials + scalars
   double* v0buf = nullptr;
+  double* lzq[2] = {};           // Lanczos vectors (made on first use)
+  double* lzcoef = nullptr;      // Lanczos coefficients
   float *Tt = nullptr, *St = nullptr, *Rt = nullptr, *BobsT = nullptr;
   DeviceArena arena;
 };
@@ -741,6 +743,49 @@ hipError_t run_iteration(sfista_fft* h) {
   return hipSuccess;
 }
 
+template <class T>
+bool take(DeviceArena& ar, T*& p, size_t count, hipStream_t s) {
+  p = static_cast<T*>(ar.alloc_zero(count * sizeof(T), s));
+  return p != nullptr;
+}
+
+// Lanczos estimate of L, the recurrence of the GEMM form's run_lanczos with
+// A_s^T A_s applied by the transform passes.
+hipError_t run_lanczos(sfista_fft* h, const double* v0, int steps, double* L_out) {
+  const long mn = (long)h->m * h->n;
+  double* scal = h->red + RED_BLOCKS;
+  DeviceArena& ar = h->arena;
+  if ((!h->lzq[0] && !take(ar, h->lzq[0], mn, h->s)) || (!h->lzq[1] && !take(ar, h->lzq[1], mn, h->s)) ||
+      !take(ar, h->lzcoef, (size_t)steps * 2, h->s))
+    return hipErrorOutOfMemory;
+  double* coef = h->lzcoef;
+  hipError_t e;
+  if ((e = sumsq(DoubleSq{v0}, mn, h->red, scal, h->s)) != hipSuccess) return e;
+  hipLaunchKernelGGL(lanczos_scale_kernel, dim3(EW_BLOCKS_FFT), dim3(256), 0, h->s, v0, scal, h->lzq[0], mn);
+  int cur = 0;
+  for (int j = 0; j < steps; ++j) {
+    double* q = h->lzq[cur];
+    double* qo = h->lzq[cur ^ 1];      // q_{j-1}, then q_{j+1}
+    if ((e = normal_op(h, q, nullptr, nullptr, h->aux)) != hipSuccess) return e;
+    if ((e = sumf(DoubleDot{q, h->aux}, mn, h->red, coef + 2 * j, h->s)) != hipSuccess) return e;
+    hipLaunchKernelGGL(lanczos_orth_kernel, dim3(RED_BLOCKS), dim3(RED_THREADS), 0, h->s, h->aux, q, qo, coef, j, mn,
+                       h->red);
+    hipLaunchKernelGGL(sum_partials_kernel, dim3(1), dim3(RED_THREADS), 0, h->s, h->red, RED_BLOCKS,
+                       coef + 2 * j + 1);
+    if (j + 1 < steps) {
+      hipLaunchKernelGGL(lanczos_scale_kernel, dim3(EW_BLOCKS_FFT), dim3(256), 0, h->s, h->aux, coef + 2 * j + 1, qo,
+                         mn);
+      cur ^= 1;
+    }
+  }
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  std::vector<double> hc((size_t)steps * 2);
+  if ((e = hipMemcpyAsync(hc.data(), coef, hc.size() * 8, hipMemcpyDeviceToHost, h->s)) != hipSuccess) return e;
+  if ((e = hipStreamSynchronize(h->s)) != hipSuccess) return e;
+  *L_out = lanczos_ritz_max(hc.data(), steps);
+  return hipSuccess;
+}
+
 hipError_t run_power(sfista_fft* h, const double* v0, int steps, double* L_out) {
   const long mn = (long)h->m * h->n;
   double* scal = h->red + RED_BLOCKS;
@@ -759,11 +804,6 @@ hipError_t run_power(sfista_fft* h, const double* v0, int steps, double* L_out) 
   return hipSuccess;
 }
 
-template <class T>
-bool take(DeviceArena& ar, T*& p, size_t count, hipStream_t s) {
-  p = static_cast<T*>(ar.alloc_zero(count * sizeof(T), s));
-  return p != nullptr;
-}
 
 std::vector<float2> twiddles(int N) {
   std::vector<float2> t(N);
@@ -814,7 +854,8 @@ int fft_setup(sfista_fft* h, const double* Bobs, const double* hgen, const doubl
     return hip_fail(e, "setup");
   h->bobs_norm = sqrt(ss);
   if (!(h->L > 0.0)) {
-    const int steps = p->power_iters > 0 ? p->power_iters : 30;
+    const bool lanczos = p->l_estimate == SFISTA_L_LANCZOS;
+    const int steps = p->power_iters > 0 ? p->power_iters : (lanczos ? 12 : 30);
     const double* v0 = p->v0;
     if (!v0) {
       if (!take(ar, h->v0buf, mn, s)) return set_error(SFISTA_ERR_NOMEM, "device allocation failed");
@@ -822,7 +863,8 @@ int fft_setup(sfista_fft* h, const double* Bobs, const double* hgen, const doubl
       v0 = h->v0buf;
     }
     double L = 0.0;
-    if ((e = run_power(h, v0, steps, &L)) != hipSuccess) return hip_fail(e, "power iteration");
+    if ((e = lanczos ? run_lanczos(h, v0, steps, &L) : run_power(h, v0, steps, &L)) != hipSuccess)
+      return hip_fail(e, lanczos ? "Lanczos estimate of L" : "power iteration");
     if (!isfinite(L) || !(L > 0.0)) return set_error(SFISTA_ERR_NONFINITE, "Lipschitz estimate is %g", L);
     h->L = L;
   }
@@ -853,6 +895,8 @@ int sfista_fft_setup(const double* Bobs, int m, int n, const double* h, const do
   if (!isfinite(p->lambda) || p->lambda < 0.0) return set_error(SFISTA_ERR_ARG, "lambda must be finite and >= 0");
   if (!isfinite(p->L)) return set_error(SFISTA_ERR_ARG, "L must be finite");
   if (p->power_iters < 0) return set_error(SFISTA_ERR_ARG, "power_iters must be >= 0");
+  if (p->l_estimate != SFISTA_L_POWER && p->l_estimate != SFISTA_L_LANCZOS)
+    return set_error(SFISTA_ERR_ARG, "unknown l_estimate %d", p->l_estimate);
   sfista_fft* f = new (std::nothrow) sfista_fft();
   if (!f) return set_error(SFISTA_ERR_NOMEM, "host allocation failed");
   f->m = m; f->n = n; f->r = r; f->l = l; f->q = q; f->refl = bc == SFISTA_BC_REFLEXIVE ? 1 : 0;

@@ -2,6 +2,10 @@
 // sFISTA iteration (Algorithm 2).
 #pragma once
 
+#include <math.h>
+
+#include <vector>
+
 #include "common.hpp"
 
 namespace sf {
@@ -70,6 +74,87 @@ hipError_t sumsq(F f, long count, double* partial, double* out, hipStream_t s) {
   hipLaunchKernelGGL(sumsq_partial_kernel<F>, dim3(RED_BLOCKS), dim3(RED_THREADS), 0, s, f, count, partial);
   hipLaunchKernelGGL(sum_partials_kernel, dim3(1), dim3(RED_THREADS), 0, s, partial, RED_BLOCKS, out);
   return hipGetLastError();
+}
+
+// ------------------------------------------------------------- Lanczos
+// Symmetric Lanczos on M = A_s^T A_s for the estimate of L (Section 4 takes
+// L from a Lanczos estimate of the operator norm).  Step j (0-based) keeps
+// its coefficients on the device: coef[2j] = alpha_j = <q_j, M q_j> and
+// coef[2j+1] = beta_j^2 = ||w_j||^2 after the three-term orthogonalisation.
+
+// w <- w - alpha_j q_j - beta_{j-1} q_{j-1}, and the block partials of ||w||^2
+// (launch with RED_BLOCKS x RED_THREADS, then sum_partials_kernel).
+static __global__ __launch_bounds__(RED_THREADS) void lanczos_orth_kernel(double* w, const double* q,
+                                                                          const double* qprev, const double* coef,
+                                                                          int j, long count, double* partial) {
+  __shared__ double sh[RED_THREADS / 64];
+  const double a = coef[2 * j];
+  const double b = j > 0 ? sqrt(coef[2 * j - 1]) : 0.0;
+  double acc = 0.0;
+  for (long e = blockIdx.x * (long)RED_THREADS + threadIdx.x; e < count; e += (long)RED_BLOCKS * RED_THREADS) {
+    double v = w[e] - a * q[e];
+    if (j > 0) v -= b * qprev[e];
+    w[e] = v;
+    acc += v * v;
+  }
+  const double t = block_sum(acc, sh);
+  if (threadIdx.x == 0) partial[blockIdx.x] = t;
+}
+
+// q = w / sqrt(*ss); zero when ss is 0 (the Krylov space is invariant and
+// the host stops reading coefficients there).
+static __global__ void lanczos_scale_kernel(const double* w, const double* ss, double* q, long count) {
+  const double s = *ss > 0.0 ? 1.0 / sqrt(*ss) : 0.0;
+  for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < count; e += (long)gridDim.x * blockDim.x)
+    q[e] = w[e] * s;
+}
+
+// Number of eigenvalues below x of the symmetric tridiagonal matrix with
+// diagonal a and off-diagonal b (Sylvester's law of inertia on the LDL^T
+// pivots of T - x I).
+inline int sturm_count_below(const double* a, const double* b, int k, double x) {
+  int count = 0;
+  double d = 1.0;
+  for (int i = 0; i < k; ++i) {
+    d = (a[i] - x) - (i > 0 ? b[i - 1] * b[i - 1] / d : 0.0);
+    if (d == 0.0) d = -1e-300;
+    if (d < 0.0) ++count;
+  }
+  return count;
+}
+
+// Largest eigenvalue of that tridiagonal matrix by bisection inside its
+// Gershgorin interval, to the last bit.  NaN if a coefficient is not finite.
+inline double tridiag_max_eig(const double* a, const double* b, int k) {
+  if (k < 1) return NAN;
+  double lo = INFINITY, hi = -INFINITY;
+  for (int i = 0; i < k; ++i) {
+    const double rad = (i > 0 ? fabs(b[i - 1]) : 0.0) + (i + 1 < k ? fabs(b[i]) : 0.0);
+    if (!isfinite(a[i]) || !isfinite(rad)) return NAN;
+    lo = fmin(lo, a[i] - rad);
+    hi = fmax(hi, a[i] + rad);
+  }
+  for (int it = 0; it < 4096; ++it) {
+    const double mid = 0.5 * (lo + hi);
+    if (!(mid > lo && mid < hi)) break;
+    if (sturm_count_below(a, b, k, mid) == k) hi = mid;
+    else lo = mid;
+  }
+  return hi;
+}
+
+// The estimate from the host copy of coef for `steps` steps: the largest
+// Ritz value of the tridiagonal matrix of alpha_0.. and beta_0.., cut at
+// the first vanishing beta_j (an invariant Krylov space).
+inline double lanczos_ritz_max(const double* coef, int steps) {
+  std::vector<double> a, b;
+  for (int j = 0; j < steps; ++j) {
+    a.push_back(coef[2 * j]);
+    const double bb = coef[2 * j + 1];
+    if (j + 1 == steps || !(bb > 0.0)) break;
+    b.push_back(sqrt(bb));
+  }
+  return tridiag_max_eig(a.data(), b.data(), (int)a.size());
 }
 
 // ------------------------------------------------------------- state views

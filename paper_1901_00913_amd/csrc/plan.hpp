@@ -29,7 +29,10 @@ struct sfista_plan {
   void* st[2] = {};
   double* aux = nullptr;      // m x n FP64 scratch (power iterate, copies)
   double* red = nullptr;      // reduction partials [RED_BLOCKS] + scalars
-  double* v0buf = nullptr;    // m x n start of the power iteration (made on first use)
+  double* v0buf = nullptr;    // m x n start of the estimate of L (made on first use)
+  double* lzq[2] = {};        // m x n Lanczos vectors q_j, q_{j-1} (made on first use)
+  double* lzcoef = nullptr;   // 2 x steps Lanczos coefficients (alpha_j, beta_j^2)
+  int lzcap = 0;              // steps lzcoef holds
   void* ws = nullptr;         // K-split partials of the planned products
   sf::GemmPlanDev pl[4];      // work lists of F1, F2, G1, G2
   double bobs_norm = 0.0;
@@ -101,6 +104,8 @@ inline int validate_problem(const double* Bobs, int m, int n, const double* A, c
   if (p->precision < SFISTA_FP64 || p->precision > SFISTA_BF16X3)
     return set_error(SFISTA_ERR_UNSUPPORTED, "unknown precision %d", p->precision);
   if (p->power_iters < 0) return set_error(SFISTA_ERR_ARG, "power_iters must be >= 0");
+  if (p->l_estimate != SFISTA_L_POWER && p->l_estimate != SFISTA_L_LANCZOS)
+    return set_error(SFISTA_ERR_ARG, "unknown l_estimate %d", p->l_estimate);
   return SFISTA_OK;
 }
 

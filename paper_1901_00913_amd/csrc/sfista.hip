@@ -175,6 +175,53 @@ hipError_t run_power(sfista_plan* h, const double* v0, int steps, double* L_out)
   return hipSuccess;
 }
 
+// Lanczos estimate of L (the coefficient recurrence of lanczos_orth_kernel):
+// q_0 = v0 / ||v0||; step j forms w = A_s^T A_s q_j through the plan's four
+// products, alpha_j = <q_j, w>, orthogonalises w against q_j and q_{j-1},
+// stores ||w||^2 and normalises w into q_{j+1}.  The coefficients stay on the
+// device until the end; the host takes the largest Ritz value.
+template <int MODE>
+hipError_t run_lanczos(sfista_plan* h, const double* v0, int steps, double* L_out) {
+  const long mn = (long)h->m * h->n;
+  double* partial = h->red;
+  double* scal = h->red + RED_BLOCKS;
+  for (int i = 0; i < 2; ++i)
+    if (!h->lzq[i] && !(h->lzq[i] = static_cast<double*>(h->mem->alloc_zero((size_t)mn * 8, h->s))))
+      return hipErrorOutOfMemory;
+  if (h->lzcap < steps) {
+    if (!(h->lzcoef = static_cast<double*>(h->mem->alloc_zero((size_t)steps * 2 * 8, h->s))))
+      return hipErrorOutOfMemory;
+    h->lzcap = steps;
+  }
+  double* coef = h->lzcoef;
+  hipError_t e;
+  if ((e = sumsq(DoubleSq{v0}, mn, partial, scal, h->s)) != hipSuccess) return e;
+  hipLaunchKernelGGL(lanczos_scale_kernel, dim3(EW_BLOCKS), dim3(EW_THREADS), 0, h->s, v0, scal, h->lzq[0], mn);
+  int cur = 0;
+  for (int j = 0; j < steps; ++j) {
+    double* q = h->lzq[cur];
+    double* qo = h->lzq[cur ^ 1];      // q_{j-1}, then q_{j+1}
+    hipLaunchKernelGGL(to_planes_kernel<MODE>, dim3(EW_BLOCKS), dim3(EW_THREADS), 0, h->s, q, nullptr, h->Y[0],
+                       h->Y[1], h->ldY, h->m, h->n);
+    if ((e = run_normal<MODE>(h, h->Y, h->ldY, nullptr, h->aux)) != hipSuccess) return e;
+    if ((e = sumf(DoubleDot{q, h->aux}, mn, partial, coef + 2 * j, h->s)) != hipSuccess) return e;
+    hipLaunchKernelGGL(lanczos_orth_kernel, dim3(RED_BLOCKS), dim3(RED_THREADS), 0, h->s, h->aux, q, qo, coef, j, mn,
+                       partial);
+    hipLaunchKernelGGL(sum_partials_kernel, dim3(1), dim3(RED_THREADS), 0, h->s, partial, RED_BLOCKS, coef + 2 * j + 1);
+    if (j + 1 < steps) {
+      hipLaunchKernelGGL(lanczos_scale_kernel, dim3(EW_BLOCKS), dim3(EW_THREADS), 0, h->s, h->aux, coef + 2 * j + 1,
+                         qo, mn);
+      cur ^= 1;
+    }
+  }
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  std::vector<double> hc((size_t)steps * 2);
+  if ((e = hipMemcpyAsync(hc.data(), coef, hc.size() * 8, hipMemcpyDeviceToHost, h->s)) != hipSuccess) return e;
+  if ((e = hipStreamSynchronize(h->s)) != hipSuccess) return e;
+  *L_out = lanczos_ritz_max(hc.data(), steps);
+  return hipSuccess;
+}
+
 template <int MODE>
 hipError_t run_pack(sfista_plan* h, const double* A, const double* B) {
   const int m = h->m, n = h->n, r = h->r;
@@ -291,7 +338,8 @@ int load_problem(sfista_plan* h, const double* Bobs, const double* A, const doub
   h->bobs_norm = sqrt(ss);
 
   if (!(h->L > 0.0)) {
-    const int steps = p->power_iters > 0 ? p->power_iters : 30;
+    const bool lanczos = p->l_estimate == SFISTA_L_LANCZOS;
+    const int steps = p->power_iters > 0 ? p->power_iters : (lanczos ? 12 : 30);
     const double* v0 = p->v0;
     if (!v0) {
       // fixed internal start: a deterministic hash pattern
@@ -302,7 +350,8 @@ int load_problem(sfista_plan* h, const double* Bobs, const double* A, const doub
       v0 = h->v0buf;
     }
     double L = 0.0;
-    if ((e = run_power<MODE>(h, v0, steps, &L)) != hipSuccess) return hip_fail(e, "power iteration");
+    if ((e = lanczos ? run_lanczos<MODE>(h, v0, steps, &L) : run_power<MODE>(h, v0, steps, &L)) != hipSuccess)
+      return hip_fail(e, lanczos ? "Lanczos estimate of L" : "power iteration");
     if (!isfinite(L) || !(L > 0.0)) return set_error(SFISTA_ERR_NONFINITE, "Lipschitz estimate is %g", L);
     h->L = L;
   }
@@ -992,7 +1041,10 @@ int sfista_batch_setup(const sfista_batch_item* items, int count, const sfista_p
   if (max_iters < 1 || max_iters > (1 << 24)) return set_error(SFISTA_ERR_ARG, "max_iters must lie in [1, 2^24]");
   if (common->precision < SFISTA_FP64 || common->precision > SFISTA_BF16X3)
     return set_error(SFISTA_ERR_UNSUPPORTED, "unknown precision %d", common->precision);
-  if (common->x0 || common->v0) return set_error(SFISTA_ERR_UNSUPPORTED, "batch problems start from X_0 = 0 and an internal power start");
+  if (common->x0 || common->v0)
+    return set_error(SFISTA_ERR_UNSUPPORTED, "batch problems start from X_0 = 0 and an internal power start");
+  if (common->l_estimate == SFISTA_L_LANCZOS)
+    return set_error(SFISTA_ERR_UNSUPPORTED, "the batch estimates L by power iteration only");
   for (int i = 0; i < count; ++i) {
     sfista_params p = *common;
     p.lambda = items[i].lambda;

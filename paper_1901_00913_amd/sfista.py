@@ -42,6 +42,17 @@ BATCH_AUTOTUNE = 1
 BATCH_GRAPH = 2
 
 
+L_ESTIMATES = {"power": 0, "lanczos": 1}
+
+
+def _l_estimate(name: str) -> int:
+    """``"power"`` (power iteration) or ``"lanczos"`` (Section 4's Lanczos
+    estimate); used when ``L`` is not given, with ``power_iters`` steps."""
+    if name not in L_ESTIMATES:
+        raise ValueError(f"l_estimate must be one of {sorted(L_ESTIMATES)}, not {name!r}")
+    return L_ESTIMATES[name]
+
+
 class SfistaError(RuntimeError):
     def __init__(self, code: int, msg: str):
         super().__init__(f"sfista error {code}: {msg}")
@@ -51,7 +62,7 @@ class SfistaError(RuntimeError):
 class Params(ctypes.Structure):
     _fields_ = [("lambda_", ctypes.c_double), ("L", ctypes.c_double), ("precision", ctypes.c_int),
                 ("nonneg", ctypes.c_int), ("power_iters", ctypes.c_int), ("pair_state", ctypes.c_int),
-                ("x0", ctypes.c_void_p), ("v0", ctypes.c_void_p)]
+                ("x0", ctypes.c_void_p), ("v0", ctypes.c_void_p), ("l_estimate", ctypes.c_int)]
 
 
 class BatchItem(ctypes.Structure):
@@ -190,14 +201,15 @@ class FftSolver:
     iterates)."""
 
     def __init__(self, Bobs, h, k, l: int, q: int, bc: int, lam: float, L: Optional[float] = None,
-                 nonneg: bool = False, power_iters: int = 0, x0=None, v0=None, stream=None):
+                 nonneg: bool = False, power_iters: int = 0, x0=None, v0=None, stream=None,
+                 l_estimate: str = "power"):
         m, n = Bobs.shape
         r = h.shape[0]
         if h.shape != (r, m) or k.shape != (r, n):
             raise ValueError("h must be (r, m) and k (r, n) for Bobs of shape (m, n)")
         p = Params(float(lam), float(L) if L is not None else 0.0, PRECISIONS["fp32"], int(bool(nonneg)),
                    int(power_iters), 0, _dev_f64(x0, "x0") if x0 is not None else None,
-                   _dev_f64(v0, "v0") if v0 is not None else None)
+                   _dev_f64(v0, "v0") if v0 is not None else None, _l_estimate(l_estimate))
         hd = ctypes.c_void_p()
         self._h = None
         self.shape = (m, n)
@@ -249,7 +261,7 @@ class Solver:
 
     def __init__(self, Bobs, A, B, lam: float, L: Optional[float] = None, precision: str = "bf16x3",
                  nonneg: bool = False, power_iters: int = 0, pair_state: bool = True, x0=None, v0=None,
-                 stream=None):
+                 stream=None, l_estimate: str = "power"):
         m, n = Bobs.shape
         r = A.shape[0]
         if A.shape != (r, n, n) or B.shape != (r, m, m):
@@ -257,7 +269,7 @@ class Solver:
         p = Params(float(lam), float(L) if L is not None else 0.0, PRECISIONS[precision], int(bool(nonneg)),
                    int(power_iters), int(bool(pair_state)),
                    _dev_f64(x0, "x0") if x0 is not None else None,
-                   _dev_f64(v0, "v0") if v0 is not None else None)
+                   _dev_f64(v0, "v0") if v0 is not None else None, _l_estimate(l_estimate))
         h = ctypes.c_void_p()
         self._h = None
         self.shape = (m, n)

@@ -52,7 +52,7 @@ FAKE = ctypes.c_void_p(0x1000)   # never dereferenced: validation fails first
 @pytest.mark.parametrize("case,expect", [
     (dict(m=0), -1), (dict(n=-3), -1), (dict(r=0), -1), (dict(r=5, m=4, n=4), -1),
     (dict(lambda_=-1.0), -1), (dict(lambda_=float("nan")), -1), (dict(L=float("inf")), -1),
-    (dict(precision=7), -2), (dict(power_iters=-1), -1),
+    (dict(precision=7), -2), (dict(power_iters=-1), -1), (dict(l_estimate=2), -1), (dict(l_estimate=-1), -1),
 ])
 def test_setup_rejects_invalid_arguments(L, case, expect):
     m, n, r = case.pop("m", 4), case.pop("n", 4), case.pop("r", 1)
@@ -112,6 +112,8 @@ def _items(count=2, **kw):
     (2, 10, {}, dict(precision=9), -2),
     (2, 10, {}, dict(x0=0x2000), -2),             # batch problems start from zero
     (2, 10, {}, dict(power_iters=-2), -1),
+    (2, 10, {}, dict(l_estimate=1), -2),          # the batch estimates L by power iteration only
+    (2, 10, {}, dict(l_estimate=3), -1),
 ])
 def test_batch_setup_rejects_invalid_arguments(L, count, max_iters, item, common, expect):
     items = _items(max(count, 1), **item)
@@ -173,7 +175,7 @@ def test_diff_calls_reject_null(L):
 @pytest.mark.parametrize("args,expect", [
     (dict(m=0), -1), (dict(n=5000), -2), (dict(r=0), -1), (dict(r=5, m=4, n=4), -1),
     (dict(r=65, m=100, n=100), -2), (dict(l=4), -1), (dict(q=-1), -1), (dict(bc=2), -1),
-    (dict(lambda_=-1.0), -1), (dict(L=float("nan")), -1), (dict(power_iters=-1), -1),
+    (dict(lambda_=-1.0), -1), (dict(L=float("nan")), -1), (dict(power_iters=-1), -1), (dict(l_estimate=5), -1),
 ])
 def test_fft_setup_rejects_invalid_arguments(L, args, expect):
     m, n, r = args.pop("m", 4), args.pop("n", 4), args.pop("r", 1)

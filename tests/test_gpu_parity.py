@@ -189,6 +189,41 @@ def test_power_iteration_matches_oracle(sf, mode, steps, tol):
     s.close()
 
 
+@pytest.mark.parametrize("mode,steps,tol", [("fp64", 12, 1e-10), ("fp64", 40, 1e-9), ("fp32", 12, 1e-5),
+                                             ("bf16x3", 12, 1e-5), ("bf16x3", 0, 1e-5)])
+def test_lanczos_estimate_matches_oracle(sf, mode, steps, tol):
+    """Section 4's Lanczos estimate of L through the plan's GEMMs against the
+    oracle's Lanczos from the same start (steps = 0 takes the default 12);
+    40 FP64 steps run well past the loss of orthogonality."""
+    p = S.config(2, n=192)
+    K, H = _oracle_setup(p)
+    s = sf.Solver(dev(p.bobs), dev(K), dev(H), lam=p.lam, precision=mode, power_iters=steps, v0=dev(p.v0),
+                  l_estimate="lanczos")
+    Lo = O.lipschitz_lanczos(K, H, p.v0, steps or 12)
+    say(f"[lanczos] {mode} steps={steps} gpu={s.L:.12e} oracle={Lo:.12e} rel={abs(s.L - Lo) / Lo:.2e}")
+    assert math.isclose(s.L, Lo, rel_tol=tol)
+    s.close()
+
+
+@pytest.mark.parametrize("m,n,r", [(37, 53, 3), (1, 1, 1), (45, 1, 1)])
+def test_lanczos_estimate_ragged_and_degenerate(sf, m, n, r):
+    """Random factors on ragged and degenerate shapes, FP64 GEMMs: the GPU
+    Lanczos estimate against the oracle's.  A single pixel or column has
+    fewer unknowns than steps, so the recurrence meets an invariant space."""
+    rng = np.random.default_rng(100 * m + n)
+    K = rng.standard_normal((r, n, n)) / math.sqrt(n)
+    H = rng.standard_normal((r, m, m)) / math.sqrt(m)
+    v0 = rng.standard_normal((m, n))
+    s = sf.Solver(dev(np.zeros((m, n))), dev(K), dev(H), lam=0.1, precision="fp64", power_iters=20, v0=dev(v0),
+                  l_estimate="lanczos")
+    Lo = O.lipschitz_lanczos(K, H, v0, 20)
+    say(f"[lanczos {m}x{n} r={r}] gpu={s.L:.12e} oracle={Lo:.12e}")
+    assert math.isclose(s.L, Lo, rel_tol=1e-9)
+    if m * n <= 20:
+        assert math.isclose(s.L, O.lipschitz_dense(O.kron_sum_dense(K, H)), rel_tol=1e-9)
+    s.close()
+
+
 @pytest.fixture(scope="module")
 def cfg2():
     """Configuration 2 (512x512, reflexive, r = 5, lambda = 0.01, 200
@@ -372,3 +407,10 @@ def test_zero_factors_are_rejected(sf):
     with pytest.raises(sf.SfistaError) as ei:
         sf.FftSolver(z(m, n), z(r, m), z(r, n), m // 2, n // 2, 1, lam=0.1, power_iters=5)
     assert ei.value.code == sf.SFISTA_ERR_NONFINITE
+    for est in ("lanczos",):
+        with pytest.raises(sf.SfistaError) as ei:
+            sf.Solver(z(m, n), z(r, n, n), z(r, m, m), lam=0.1, precision="fp64", power_iters=5, l_estimate=est)
+        assert ei.value.code == sf.SFISTA_ERR_NONFINITE
+        with pytest.raises(sf.SfistaError) as ei:
+            sf.FftSolver(z(m, n), z(r, m), z(r, n), m // 2, n // 2, 1, lam=0.1, power_iters=5, l_estimate=est)
+        assert ei.value.code == sf.SFISTA_ERR_NONFINITE
