@@ -129,6 +129,24 @@ typedef struct sfista_plan* sfista_handle;
 int kron_approx(const double* P, int m, int n, int l, int q, int bc, int r,
                 double* A, double* B, double* sigma, double* eps_s, hipStream_t stream);
 
+/* Kronecker approximations of `count` PSFs in one call (Section 2, Theorem 1
+ * for each; the setup of a batch of images).  Every argument of kron_approx
+ * becomes a host array of `count` entries: P[i] (device) m[i] x n[i], centre
+ * (l[i], q[i]), bc[i], r[i], and the outputs A[i] (device) r[i] x n[i] x n[i]
+ * and B[i] (device) r[i] x m[i] x m[i].
+ *   sigma  (host, out, nullable) the singular values, packed: image i's r[i]
+ *          values start at entry r[0] + ... + r[i-1].
+ *   eps_s  (host, out, nullable) count entries.
+ * Every image is checked as kron_approx checks it before any work is queued
+ * (the message names the image).  Each image's kernels are those of
+ * kron_approx, queued on one of up to four internal streams of default
+ * priority so that several images run at once; they start after the work
+ * already queued on `stream`, and the call synchronises `stream` before
+ * returning.  Results equal kron_approx's bit for bit. */
+int kron_approx_batch(int count, const double* const* P, const int* m, const int* n, const int* l, const int* q,
+                      const int* bc, const int* r, double* const* A, double* const* B, double* sigma,
+                      double* eps_s, hipStream_t stream);
+
 /* The same approximation, returned as its generator vectors instead of dense
  * factors (Section 2): h (device, out) r x m and k (device, out) r x n, FP64,
  * with B_k = toep(h_k, l + 1) [+ hank(h_k, l + 1)] and A_k = toep(k_k, q + 1)

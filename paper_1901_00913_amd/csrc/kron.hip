@@ -39,6 +39,7 @@ constexpr int SUBSPACE_ITERS = 12;
 constexpr int JACOBI_SWEEPS = 40;
 constexpr int KT = 256;           // threads of the row kernels
 constexpr int ST = 1024;          // threads of the single-block kernels
+constexpr int KRON_STREAMS = 4;   // internal streams of kron_approx_batch (the device's hardware queues)
 
 struct Reflex {                   // closed-form M^{1/2} pieces for one side
   double sq_d, a_plus, a_minus;   // M^{1/2}:  sqrt(d), coefficients of w+ w+^T, w- w-^T
@@ -519,10 +520,8 @@ struct TailSq {        // P_bar[a][b] - sum_k sigma_k u_k[a] v_k[b]
   }
 };
 
-// The common body of kron_approx and kron_generators: dense factors (A, B)
-// and generators (h, k) are each optional.
-int kron_impl(const double* P, int m, int n, int l, int q, int bc, int r, double* A, double* B, double* h_out,
-              double* k_out, double* sigma, double* eps_s, hipStream_t s) {
+// Argument checks shared by every entry point of the approximation.
+int kron_check(int m, int n, int l, int q, int bc, int r) {
   if (m < 1 || n < 1) return set_error(SFISTA_ERR_ARG, "PSF size %d x %d must be positive", m, n);
   if (l < 0 || l >= m || q < 0 || q >= n) return set_error(SFISTA_ERR_ARG, "centre (%d, %d) outside the PSF", l, q);
   if (bc != SFISTA_BC_ZERO && bc != SFISTA_BC_REFLEXIVE) return set_error(SFISTA_ERR_ARG, "unknown boundary %d", bc);
@@ -530,6 +529,16 @@ int kron_impl(const double* P, int m, int n, int l, int q, int bc, int r, double
   if (r < 1 || r > mn_min) return set_error(SFISTA_ERR_ARG, "rank r=%d must lie in [1, min(m,n)]", r);
   if (r > PMAX - OVERSAMPLE) return set_error(SFISTA_ERR_UNSUPPORTED, "rank r=%d exceeds %d", r, PMAX - OVERSAMPLE);
   if ((long)m * n > (1L << 31)) return set_error(SFISTA_ERR_UNSUPPORTED, "PSF too large");
+  return SFISTA_OK;
+}
+
+// Queues the whole approximation of one (checked) PSF on s without waiting:
+// dense factors (A, B) and generators (h, k) are each optional; res (device,
+// 1 + r doubles) receives ||P_bar - sum_k sigma_k u_k v_k^T||_F^2 and then the
+// r singular values.  The work buffers are freed in stream order.
+int kron_enqueue(const double* P, int m, int n, int l, int q, int bc, int r, double* A, double* B, double* h_out,
+                 double* k_out, double* res, hipStream_t s) {
+  const int mn_min = m < n ? m : n;
   const int p = std::min(r + OVERSAMPLE, mn_min);
   const long mn = (long)m * n;
 
@@ -586,18 +595,36 @@ int kron_impl(const double* P, int m, int n, int l, int q, int bc, int r, double
   if (e == hipSuccess && h_out) e = hipMemcpyAsync(h_out, gh, (size_t)r * m * 8, hipMemcpyDeviceToDevice, s);
   if (e == hipSuccess && k_out) e = hipMemcpyAsync(k_out, gk, (size_t)r * n * 8, hipMemcpyDeviceToDevice, s);
   if (e != hipSuccess) return hip_fail(e, "kron_approx launch");
-  if ((e = sumsq(TailSq{Pb, U, V, sig_out, r, m, n}, mn, red, red + RED_BLOCKS, s)) != hipSuccess)
+  if ((e = sumsq(TailSq{Pb, U, V, sig_out, r, m, n}, mn, red, res, s)) != hipSuccess)
     return hip_fail(e, "kron_approx tail norm");
-  double tail = 0.0;
-  std::vector<double> sv(r);
-  if ((e = hipMemcpyAsync(&tail, red + RED_BLOCKS, 8, hipMemcpyDeviceToHost, s)) != hipSuccess ||
-      (e = hipMemcpyAsync(sv.data(), sig_out, r * 8, hipMemcpyDeviceToHost, s)) != hipSuccess ||
+  if ((e = hipMemcpyAsync(res + 1, sig_out, (size_t)r * 8, hipMemcpyDeviceToDevice, s)) != hipSuccess)
+    return hip_fail(e, "kron_approx results");
+  return SFISTA_OK;
+}
+
+// Host side of one result: sigma (r values) and eps_s from res (host copy).
+int kron_results(const double* res, int r, double* sigma, double* eps_s) {
+  if (sigma) for (int k = 0; k < r; ++k) sigma[k] = res[1 + k];
+  if (eps_s) *eps_s = sqrt(res[0]);
+  if (!isfinite(res[0])) return set_error(SFISTA_ERR_NONFINITE, "non-finite approximation error");
+  return SFISTA_OK;
+}
+
+// The common body of kron_approx and kron_generators.
+int kron_impl(const double* P, int m, int n, int l, int q, int bc, int r, double* A, double* B, double* h_out,
+              double* k_out, double* sigma, double* eps_s, hipStream_t s) {
+  int rc = kron_check(m, n, l, q, bc, r);
+  if (rc != SFISTA_OK) return rc;
+  DeviceArena rar;
+  double* res = static_cast<double*>(rar.alloc_zero((size_t)(1 + r) * 8, s));
+  if (!res) return set_error(SFISTA_ERR_NOMEM, "device allocation failed (%s)", rar.last_error());
+  if ((rc = kron_enqueue(P, m, n, l, q, bc, r, A, B, h_out, k_out, res, s)) != SFISTA_OK) return rc;
+  std::vector<double> hres((size_t)1 + r);
+  hipError_t e;
+  if ((e = hipMemcpyAsync(hres.data(), res, hres.size() * 8, hipMemcpyDeviceToHost, s)) != hipSuccess ||
       (e = hipStreamSynchronize(s)) != hipSuccess)
     return hip_fail(e, "kron_approx");
-  if (sigma) for (int k = 0; k < r; ++k) sigma[k] = sv[k];
-  if (eps_s) *eps_s = sqrt(tail);
-  if (!isfinite(tail)) return set_error(SFISTA_ERR_NONFINITE, "non-finite approximation error");
-  return SFISTA_OK;
+  return kron_results(hres.data(), r, sigma, eps_s);
 }
 
 }  // namespace
@@ -607,6 +634,70 @@ extern "C" int kron_approx(const double* P, int m, int n, int l, int q, int bc, 
   clear_error();
   if (!P || !A || !B) return set_error(SFISTA_ERR_ARG, "NULL device pointer");
   return kron_impl(P, m, n, l, q, bc, r, A, B, nullptr, nullptr, sigma, eps_s, s);
+}
+
+// Several PSFs at once: each image's sequence of kernels goes to one of a
+// few internal streams (round robin), so that the latency-bound launches of
+// different images overlap; results as kron_approx's, bit for bit.
+extern "C" int kron_approx_batch(int count, const double* const* P, const int* m, const int* n, const int* l,
+                                 const int* q, const int* bc, const int* r, double* const* A, double* const* B,
+                                 double* sigma, double* eps_s, hipStream_t stream) {
+  clear_error();
+  if (count < 1) return set_error(SFISTA_ERR_ARG, "count must be >= 1");
+  if (!P || !m || !n || !l || !q || !bc || !r || !A || !B) return set_error(SFISTA_ERR_ARG, "NULL argument array");
+  std::vector<long> off((size_t)count + 1, 0);
+  for (int i = 0; i < count; ++i) {
+    if (!P[i] || !A[i] || !B[i]) return set_error(SFISTA_ERR_ARG, "image %d: NULL device pointer", i);
+    const int rc = kron_check(m[i], n[i], l[i], q[i], bc[i], r[i]);
+    if (rc != SFISTA_OK) {
+      const std::string msg = last_error_slot();
+      return set_error(rc, "image %d: %s", i, msg.c_str());
+    }
+    off[i + 1] = off[i] + 1 + r[i];
+  }
+  DeviceArena rar;
+  double* res = static_cast<double*>(rar.alloc_zero((size_t)off[count] * 8, stream));
+  if (!res) return set_error(SFISTA_ERR_NOMEM, "device allocation failed (%s)", rar.last_error());
+  const int ns = std::min(count, KRON_STREAMS);
+  std::vector<hipStream_t> st(ns, nullptr);
+  std::vector<hipEvent_t> ev(ns + 1, nullptr);
+  int rc = SFISTA_OK;
+  hipError_t e = hipSuccess;
+  for (int k = 0; k <= ns && e == hipSuccess; ++k) e = hipEventCreateWithFlags(&ev[k], hipEventDisableTiming);
+  if (e == hipSuccess) e = hipEventRecord(ev[ns], stream);   // inputs and the cleared results are ready
+  for (int k = 0; k < ns && e == hipSuccess; ++k) {
+    e = hipStreamCreateWithFlags(&st[k], hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipStreamWaitEvent(st[k], ev[ns], 0);
+  }
+  if (e != hipSuccess) rc = hip_fail(e, "kron_approx_batch streams");
+  for (int i = 0; i < count && rc == SFISTA_OK; ++i)
+    rc = kron_enqueue(P[i], m[i], n[i], l[i], q[i], bc[i], r[i], A[i], B[i], nullptr, nullptr, res + off[i],
+                      st[i % ns]);
+  // the caller's stream waits for every internal stream (also after a failure,
+  // so that nothing queued outlives the call)
+  for (int k = 0; k < ns; ++k) {
+    if (!st[k] || !ev[k]) continue;
+    if (hipEventRecord(ev[k], st[k]) != hipSuccess || hipStreamWaitEvent(stream, ev[k], 0) != hipSuccess)
+      (void)hipStreamSynchronize(st[k]);
+  }
+  std::vector<double> hres((size_t)off[count]);
+  if (rc == SFISTA_OK &&
+      ((e = hipMemcpyAsync(hres.data(), res, hres.size() * 8, hipMemcpyDeviceToHost, stream)) != hipSuccess))
+    rc = hip_fail(e, "kron_approx_batch results");
+  if ((e = hipStreamSynchronize(stream)) != hipSuccess && rc == SFISTA_OK) rc = hip_fail(e, "kron_approx_batch");
+  for (int k = 0; k < ns; ++k) if (st[k]) (void)hipStreamDestroy(st[k]);
+  for (hipEvent_t x : ev) if (x) (void)hipEventDestroy(x);
+  if (rc != SFISTA_OK) return rc;
+  long so = 0;
+  for (int i = 0; i < count; ++i) {
+    const int ri = kron_results(hres.data() + off[i], r[i], sigma ? sigma + so : nullptr, eps_s ? eps_s + i : nullptr);
+    if (ri != SFISTA_OK) {
+      const std::string msg = last_error_slot();
+      return set_error(ri, "image %d: %s", i, msg.c_str());
+    }
+    so += r[i];
+  }
+  return SFISTA_OK;
 }
 
 extern "C" int kron_generators(const double* P, int m, int n, int l, int q, int bc, int r, double* h, double* k,

@@ -36,7 +36,7 @@ EXPORTS = ("kron_approx", "sfista_setup", "sfista_step", "sfista_solve", "sfista
            "sfista_batch_destroy", "sfista_batch_set_tiles", "sfista_diff_setup", "sfista_diff_forward", "sfista_diff_backward",
            "sfista_diff_get_L", "sfista_diff_destroy", "sfista_diff_update", "sfista_release_cached",
            "kron_generators", "sfista_fft_setup", "sfista_fft_step", "sfista_fft_solve", "sfista_fft_apply",
-           "sfista_fft_get_L", "sfista_fft_destroy")
+           "sfista_fft_get_L", "sfista_fft_destroy", "kron_approx_batch")
 
 BATCH_AUTOTUNE = 1
 BATCH_GRAPH = 2
@@ -119,6 +119,9 @@ def lib() -> ctypes.CDLL:
     L.sfista_diff_destroy.restype = None
     L.sfista_release_cached.argtypes = []
     L.kron_generators.argtypes = [vp, i, i, i, i, i, i, vp, vp, vp, vp, vp]
+    ip = ctypes.POINTER(i)
+    L.kron_approx_batch.argtypes = [i, ctypes.POINTER(vp), ip, ip, ip, ip, ip, ip, ctypes.POINTER(vp),
+                                    ctypes.POINTER(vp), vp, vp, vp]
     L.sfista_fft_setup.argtypes = [vp, i, i, vp, vp, i, i, i, i, ctypes.POINTER(Params), vp, ctypes.POINTER(vp)]
     L.sfista_fft_step.argtypes = [vp, i]
     L.sfista_fft_solve.argtypes = [vp, i, d, vp, ctypes.POINTER(Report)]
@@ -176,6 +179,41 @@ def kron_approx(P, l: int, q: int, bc: int, r: int, stream=None):
                              ctypes.cast(sig, ctypes.c_void_p), ctypes.cast(ctypes.byref(eps), ctypes.c_void_p),
                              _stream(stream)))
     return A, B, np.array(sig[:r]), eps.value
+
+
+def kron_approx_many(Ps, centers, bcs, rs, stream=None):
+    """:func:`kron_approx` for several PSFs in one call (several images in
+    flight on the device): ``Ps`` device float64 tensors, ``centers`` their
+    ``(l, q)``, ``bcs`` and ``rs`` one value or one per PSF.  Returns a list
+    of ``(A, B, sigma, eps_s)``, bit for bit those of :func:`kron_approx`."""
+    import torch
+    cnt = len(Ps)
+    if cnt == 0:
+        return []
+    bcs = list(bcs) if isinstance(bcs, (list, tuple)) else [bcs] * cnt
+    rs = list(rs) if isinstance(rs, (list, tuple)) else [rs] * cnt
+    if len(centers) != cnt or len(bcs) != cnt or len(rs) != cnt:
+        raise ValueError("centers, bcs and rs need one entry per PSF")
+    ints = lambda v: (ctypes.c_int * cnt)(*[int(x) for x in v])
+    ptrs = lambda v: (ctypes.c_void_p * cnt)(*v)
+    As, Bs, pP = [], [], []
+    for P, r in zip(Ps, rs):
+        m, n = P.shape
+        pP.append(_dev_f64(P, "P"))
+        As.append(torch.empty((r, n, n), dtype=torch.float64, device=P.device))
+        Bs.append(torch.empty((r, m, m), dtype=torch.float64, device=P.device))
+    sig = (ctypes.c_double * max(sum(rs), 1))()
+    eps = (ctypes.c_double * cnt)()
+    _check(lib().kron_approx_batch(cnt, ptrs(pP), ints(P.shape[0] for P in Ps), ints(P.shape[1] for P in Ps),
+                                   ints(c[0] for c in centers), ints(c[1] for c in centers), ints(bcs), ints(rs),
+                                   ptrs(A.data_ptr() for A in As), ptrs(B.data_ptr() for B in Bs),
+                                   ctypes.cast(sig, ctypes.c_void_p), ctypes.cast(eps, ctypes.c_void_p),
+                                   _stream(stream)))
+    out, o = [], 0
+    for i in range(cnt):
+        out.append((As[i], Bs[i], np.array(sig[o:o + rs[i]]), eps[i]))
+        o += rs[i]
+    return out
 
 
 def kron_generators(P, l: int, q: int, bc: int, r: int, stream=None):

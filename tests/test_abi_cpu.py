@@ -84,6 +84,34 @@ def test_kron_approx_rejects_invalid_arguments(L, args, expect):
     assert L.kron_approx(FAKE, m, n, l, q, bc, r, FAKE, FAKE, None, None, None) == expect
 
 
+def _kron_batch_call(L, imgs, P=FAKE, A=FAKE, B=FAKE, count=None):
+    cnt = len(imgs) if count is None else count
+    k = max(len(imgs), 1)
+    col = lambda j: (ctypes.c_int * k)(*[im[j] for im in imgs] or [0])
+    ptr = lambda v: (ctypes.c_void_p * k)(*[v] * k)
+    return L.kron_approx_batch(cnt, ptr(P), col(0), col(1), col(2), col(3), col(4), col(5), ptr(A), ptr(B),
+                               None, None, None)
+
+
+@pytest.mark.parametrize("bad,expect", [
+    ((4, 4, 4, 1, 0, 1), -1), ((4, 4, 1, 1, 2, 1), -1), ((4, 4, 1, 1, 0, 5), -1), ((64, 64, 1, 1, 0, 40), -2),
+])
+def test_kron_batch_checks_every_image_before_queuing(L, bad, expect):
+    """One bad image among good ones: the call fails with kron_approx's code
+    and names the image, and queues nothing (no device is touched here)."""
+    good = (8, 8, 4, 4, 1, 2)
+    assert _kron_batch_call(L, [good, good, bad]) == expect
+    assert b"image 2" in L.sfista_last_error()
+
+
+def test_kron_batch_rejects_null_and_empty(L):
+    good = (8, 8, 4, 4, 1, 2)
+    assert _kron_batch_call(L, [good], count=0) == -1
+    assert _kron_batch_call(L, [good, good], P=None) == -1
+    assert _kron_batch_call(L, [good], B=None) == -1
+    assert L.kron_approx_batch(1, None, None, None, None, None, None, None, None, None, None, None, None) == -1
+
+
 def test_handle_calls_reject_null(L):
     assert L.sfista_step(None, 1) == -1
     assert L.sfista_solve(None, 1, 0.0, None, None) == -1

@@ -234,3 +234,28 @@ def test_batched_power_iteration_matches_lone_plans(sf, case, mode, tol):
         say(f"[batch power {mode}] {p.name}: batch L {rp['L']:.15g} lone {Ls:.15g}")
         assert math.isclose(rp["L"], Ls, rel_tol=tol)
         assert rel(host(xb), host(X)) < (1e-10 if mode == "fp64" else 1e-4)
+
+
+def test_kron_approx_many_equals_single_calls(sf):
+    """The batched Kronecker setup of nine PSFs (more images than internal
+    streams; both boundaries, ragged sizes, ranks 1..6) equals kron_approx
+    called image by image, bit for bit: factors, sigma and eps_s."""
+    import torch
+    shapes = [(33, 47, 2, O.BC_ZERO), (64, 48, 3, O.BC_REFLEXIVE), (128, 128, 5, O.BC_REFLEXIVE),
+              (200, 136, 1, O.BC_ZERO), (257, 130, 4, O.BC_REFLEXIVE), (40, 40, 6, O.BC_ZERO),
+              (96, 160, 2, O.BC_REFLEXIVE), (17, 9, 3, O.BC_ZERO), (300, 300, 5, O.BC_REFLEXIVE)]
+    Ps, centers, bcs, rs = [], [], [], []
+    for t, (m, n, r, bc) in enumerate(shapes):
+        c = (m // 2 - t % 3, n // 2 + t % 2)
+        Ps.append(dev(S.gaussian_psf(m, n, (1.0 + 0.3 * t, 2.5), 15.0 * t, c)))
+        centers.append(c)
+        bcs.append(bc)
+        rs.append(r)
+    many = sf.kron_approx_many(Ps, centers, bcs, rs)
+    torch.cuda.synchronize()
+    for i, (P, c, bc, r) in enumerate(zip(Ps, centers, bcs, rs)):
+        A, B, sig, eps = sf.kron_approx(P, c[0], c[1], bc, r)
+        Am, Bm, sigm, epsm = many[i]
+        say(f"[kron many {i}] {tuple(P.shape)} r={r} eps {eps:.6e}")
+        assert torch.equal(A, Am) and torch.equal(B, Bm)
+        assert np.array_equal(sig, sigm) and eps == epsm
