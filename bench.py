@@ -350,6 +350,9 @@ def main():
     ap.add_argument("--l-estimate", default="lanczos", choices=["lanczos", "power"],
                     help="estimate of L in each step (Section 4 uses Lanczos)")
     ap.add_argument("--l-steps", type=int, default=0, help="steps of that estimate (0: 12 Lanczos, 30 power)")
+    ap.add_argument("--timing-every", type=int, default=10,
+                    help="HIP-event timing of the GEMMs of every k-th iteration in the timed steps (each event "
+                         "leaves a few-microsecond gap, so timing every iteration would slow the step it times)")
     ap.add_argument("--cpu-iters", type=int, default=3, help="oracle iterations timed for cpu_baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp32-compare", action="store_true")
@@ -406,7 +409,7 @@ def main():
         s = sfista.Solver(Bobs, A, B, lam=lam, precision=args.precision, power_iters=args.l_steps, v0=v0,
                           l_estimate=args.l_estimate)
         if timing:
-            s.set_timing(True)
+            s.set_timing(args.timing_every)
         _, rep = s.solve(iters, want_x=False)
         kt = s.kernel_times() if timing else None
         L = s.L
@@ -531,7 +534,7 @@ def main():
                      "frac": achieved / peak, "traffic": measured_traffic(dom, args.precision, m, n, r),
                      "flops_basis": "executed MFMA flops per launch (bf16x3: 3 bf16 products of 2*M*N*K)",
                      "achieved_algorithmic": achieved_alg, "avg_launch_ms": gstat[dom]["avg_ms"],
-                     "launches": gstat[dom]["launches"]},
+                     "launches": gstat[dom]["launches"], "timed_every": args.timing_every},
         "cpu_baseline": cpu,
         "extra": extra,
     }

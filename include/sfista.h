@@ -192,14 +192,18 @@ int sfista_apply(sfista_handle h, const double* X, double* AX, double* AtAX);
 
 /* Per-kernel timing of the iteration's four GEMMs (F1: T_k = Y A_k^T,
  * F2: R = sum_k B_k T_k - Bobs, G1: S_k = B_k^T R, G2: sum_k S_k A_k with the
- * fused update).  While enabled, every GEMM launch of sfista_step /
- * sfista_solve is bracketed by HIP events on the plan's stream.
+ * fused update).  With every = k >= 1 the GEMM launches of every k-th
+ * iteration of sfista_step / sfista_solve (those begun after a multiple of k
+ * completed iterations) are bracketed by HIP events on the plan's stream;
+ * every = 1 times them all, 0 turns timing off, a negative value is an
+ * argument error.  Each event leaves a gap of a few microseconds before the
+ * next kernel, so a sample (k = 10, say) disturbs the run less.
  * sfista_kernel_times synchronises the stream and returns, per GEMM, the
  * mean device time in milliseconds (avg_ms, host, 8 entries) and the number
  * of timed launches (launches, host, 8 entries): index 0..3 = the GEMM kernel
  * of F1, F2, G1, G2; index 4..7 = the reduction of their K-split tiles
  * (0 when a product has none).  The samples are then cleared. */
-int sfista_set_timing(sfista_handle h, int enable);
+int sfista_set_timing(sfista_handle h, int every);
 int sfista_kernel_times(sfista_handle h, double* avg_ms, long* launches);
 
 /* ------------------------------------------------------------------------

@@ -37,7 +37,7 @@ struct sfista_plan {
   sf::GemmPlanDev pl[4];      // work lists of F1, F2, G1, G2
   double bobs_norm = 0.0;
   // optional per-GEMM event timing
-  int timing = 0;
+  int timing = 0;              // 0 off, k >= 1: the products of every k-th iteration
   std::vector<hipEvent_t> ev_pool;
   size_t ev_used = 0;
   std::vector<std::pair<int, size_t>> ev_marks;   // (gemm kind, index of the start event)

@@ -30,12 +30,14 @@ hipEvent_t next_event(sfista_plan* h) {
   return h->ev_pool[h->ev_used++];
 }
 
-// Brackets one GEMM launch with events when timing is enabled: start, after
-// the GEMM kernel (mid_ev, recorded by launch_planned) and after its split
-// reduction.
+// Brackets one GEMM launch with events when timing is on for this iteration
+// (every h->timing-th one): start, after the GEMM kernel (mid_ev, recorded by
+// launch_planned) and after its split reduction.  Each event record leaves a
+// gap of several microseconds before the next kernel, so sampling keeps the
+// timed iterations close to untimed ones.
 template <class F>
 hipError_t timed(sfista_plan* h, int kind, F&& launch) {
-  if (!h->timing) return launch();
+  if (h->timing <= 0 || h->iter % h->timing != 0) return launch();
   const size_t idx = h->ev_used;
   hipEvent_t a = next_event(h), mid = next_event(h), b = next_event(h);
   if (!a || !mid || !b) return hipErrorOutOfMemory;
@@ -541,10 +543,11 @@ int sfista_apply(sfista_handle h, const double* X, double* AX, double* AtAX) {
   return SFISTA_OK;
 }
 
-int sfista_set_timing(sfista_handle h, int enable) {
+int sfista_set_timing(sfista_handle h, int every) {
   clear_error();
   if (!h) return set_error(SFISTA_ERR_ARG, "NULL handle");
-  h->timing = enable ? 1 : 0;
+  if (every < 0) return set_error(SFISTA_ERR_ARG, "every must be >= 0");
+  h->timing = every;
   return SFISTA_OK;
 }
 

@@ -343,8 +343,10 @@ class Solver:
                                   atax.data_ptr() if want_atax else None))
         return ax, atax
 
-    def set_timing(self, enable: bool = True):
-        _check(lib().sfista_set_timing(self._h, int(bool(enable))))
+    def set_timing(self, every: int = 1):
+        """Time the GEMMs of every ``every``-th iteration (``True`` = 1: all of
+        them; 0 or ``False``: off)."""
+        _check(lib().sfista_set_timing(self._h, int(every)))
 
     def kernel_times(self):
         """Mean device milliseconds and launch counts since the last call:

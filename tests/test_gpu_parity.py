@@ -364,6 +364,18 @@ def test_kernel_times_report_each_launch(sf):
     for g in range(4):
         assert cnt[4 + g] in (0, 10)
         assert (ms[4 + g] > 0.0) == (cnt[4 + g] == 10)
+    # a sample: the next ten iterations begin after 10, 11, ..., 19 completed
+    # ones, of which 12, 15 and 18 are multiples of 3
+    s.set_timing(3)
+    s.solve(10, want_x=False)
+    ms, cnt = s.kernel_times()
+    assert cnt[:4] == [3, 3, 3, 3]
+    s.set_timing(0)
+    s.solve(5, want_x=False)
+    ms, cnt = s.kernel_times()
+    assert cnt[:4] == [0, 0, 0, 0]
+    with pytest.raises(sf.SfistaError):
+        s.set_timing(-1)
     s.close()
 
 
