@@ -204,6 +204,74 @@ def run_diff(args, dev, steps, warmup):
     return {"line": line, "summary": summary}
 
 
+def run_shard(args, dev, steps, warmup):
+    """One GPU's share of the 2048^2, r = 5 image under row-block sharding
+    over 8 GPUs: a 256 x 2048 block.  Its row-local products have the shard's
+    exact shapes, F1 (T = Y A^T: M = r n = 10240, N = 256, K = 2048) and G2
+    (sum S_k A_k: M = 256, N = 2048, K = r n = 10240); F2 and G1 of a
+    256-row image are not the shard's (those mix rows across GPUs).  A step is
+    300 BF16X3 iterations on a synthetic 256 x 2048 problem (its own PSF and
+    factors), with the GEMMs of every tenth iteration timed."""
+    import numpy as np
+    import torch
+
+    import synth as S
+    from paper_1901_00913_amd import sfista
+
+    m, n, r, iters, G = 256, 2048, 5, args.iters, 8
+    psf = S.gaussian_psf(m, n, sigma=(4.0, 12.0), theta_deg=30.0)
+    l, q = m // 2, n // 2
+    x = S.make_image(m, n, 1400)
+    bobs = S.add_noise(S.blur(x, psf, (l, q), 1), 0.01, 2400)
+    P = torch.as_tensor(psf).to(dev)
+    Bobs = torch.as_tensor(bobs).to(dev)
+    A, B, _, _ = sfista.kron_approx(P, l, q, 1, r)
+    s = sfista.Solver(Bobs, A, B, lam=0.02, precision="bf16x3", l_estimate="lanczos")
+    for w in range(warmup):
+        log(f"[shard] warmup step {w + 1}/{warmup}")
+        s.solve(iters, want_x=False)
+    s.set_timing(args.timing_every)
+    s.kernel_times()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        s.solve(iters, want_x=False)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    ms, cnt = s.kernel_times()
+    s.close()
+    # the same two products on the whole 2048^2 image, same box, same sampling
+    p3 = S.config(3)
+    A3, B3, _, _ = sfista.kron_approx(torch.as_tensor(p3.psf).to(dev), p3.center[0], p3.center[1], p3.bc, r)
+    s3 = sfista.Solver(torch.as_tensor(p3.bobs).to(dev), A3, B3, lam=p3.lam, L=1.0, precision="bf16x3")
+    s3.solve(20, want_x=False)
+    s3.set_timing(args.timing_every)
+    s3.kernel_times()
+    s3.solve(iters, want_x=False)
+    ms3, _ = s3.kernel_times()
+    s3.close()
+    peak = PEAK_TFLOPS["bf16x3"]
+    prods = {}
+    for name, g, (M, N, K) in (("F1", 0, (r * n, m, n)), ("G2", 3, (m, n, r * n))):
+        t, t3 = ms[g] + ms[4 + g], ms3[g] + ms3[4 + g]   # the GEMM and its split reduction
+        executed = 3 * 2.0 * M * N * K / (ms[g] * 1e-3) / 1e12
+        prods[name] = {"shape_MNK": [M, N, K], "gemm_ms": ms[g], "reduce_ms": ms[4 + g], "launches": cnt[g],
+                       "executed_tflops": executed, "mfma_frac": executed / peak, "full_image_ms": t3,
+                       "ms_over_one_eighth_of_full": t / (t3 / G)}
+        log(f"[shard] {name} {M}x{N}x{K}: {ms[g] * 1e3:.1f} + {ms[4 + g] * 1e3:.1f} us, "
+            f"{executed:.0f} TFLOP/s executed ({executed / peak:.3f} of peak); full image {t3 * 1e3:.1f} us, "
+            f"shard / (full / {G}) = {t / (t3 / G):.2f}")
+    value = iters * steps / elapsed
+    line = {
+        "metric": "sFISTA iters/sec of one GPU's row block (2048^2 image over 8 GPUs)", "value": value,
+        "unit": "iters/s", "n_gpus": 1, "steps": steps, "warmup": warmup, "ms_per_step": elapsed / steps * 1e3,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "bf16x3", "data": "synthetic",
+        "config": {"workload": f"sfista-shard-{m}x{n}-r{r}-of-2048x2048-g{G}", "image": [m, n], "rank": r,
+                   "iters": iters, "precision": "bf16x3", "parallelism": "single-gpu (one shard)"},
+        "roofline": None, "cpu_baseline": None, "extra": {"row_local_products": prods}}
+    return {"line": line, "summary": prods}
+
+
 def run_paper(args, dev, steps, warmup):
     """The paper's experiment shape (Section 4) on synthetic stand-ins: 256^2
     images, reflexive boundary, 1% noise, a defocus and a motion PSF, s = 1..5
@@ -357,12 +425,13 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp32-compare", action="store_true")
     ap.add_argument("--workload", default="precision-2048",
-                    choices=("precision-2048", "batch64", "diff8", "paper256", "fft2048"),
+                    choices=("precision-2048", "batch64", "diff8", "paper256", "fft2048", "shard2048g8"),
                     help="precision-2048: one 2048^2 image, r = 5 (default); batch64: 64 uneven images "
                          "in grouped launches replayed from a HIP graph; diff8: gradient of 50 unrolled "
                          "iterations for 8 images at 512^2, r = 4; paper256: the paper-shaped sweep "
                          "(256^2, reflexive, 1%% noise, defocus and motion blur, s = 1..5, 50 iterations); "
-                         "fft2048: the default workload in the structured-FFT form")
+                         "fft2048: the default workload in the structured-FFT form; shard2048g8: one GPU's "
+                         "256 x 2048 row block of the default image split over 8 GPUs")
     ap.add_argument("--no-batch", action="store_true", help="skip the batch64 summary in the default line")
     ap.add_argument("--no-diff", action="store_true", help="skip the diff8 summary in the default line")
     ap.add_argument("--no-fft", action="store_true", help="skip the fft2048 summary in the default line")
@@ -388,8 +457,9 @@ def main():
     sfista.lib()
     dev = torch.device("cuda:0")
 
-    if args.workload in ("batch64", "diff8", "paper256", "fft2048"):
-        res = {"batch64": run_batch, "diff8": run_diff, "paper256": run_paper, "fft2048": run_fft}[args.workload](
+    if args.workload in ("batch64", "diff8", "paper256", "fft2048", "shard2048g8"):
+        res = {"batch64": run_batch, "diff8": run_diff, "paper256": run_paper, "fft2048": run_fft,
+               "shard2048g8": run_shard}[args.workload](
             args, dev, args.steps, args.warmup)
         print(json.dumps(res["line"]), flush=True)
         return

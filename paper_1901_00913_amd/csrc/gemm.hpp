@@ -538,9 +538,16 @@ hipError_t launch_planned(GemmArgs g, const Epi& epi, const GemmPlanDev& pl, typ
   hipLaunchKernelGGL((gemm_planned_kernel<MODE, T, Epi>), dim3(pl.nitems), dim3(T::THREADS), 0, s, g, epi, ws,
                      pl.S, pl.items);
   if (mid) (void)hipEventRecord(mid, s);
-  if (pl.nsplit > 0)
-    hipLaunchKernelGGL((tile_reduce_kernel<Acc, Epi, T::BM, T::BN>), dim3(pl.nsplit, 32), dim3(256), 0, s, ws,
+  if (pl.nsplit > 0) {
+    // about 2048 blocks whatever the number of split tiles, up to one work
+    // item (eight columns or one element) per thread; each element's sum
+    // over the splits keeps its order
+    constexpr bool vec8 = std::is_same<Acc, float>::value && HasStore8<Epi>::value && ReduceVec8<Epi>::value;
+    constexpr int per_tile = T::BM * T::BN / (vec8 ? 8 : 1) / 256;
+    const int ry = std::min(per_tile, std::max(32, 2048 / pl.nsplit));
+    hipLaunchKernelGGL((tile_reduce_kernel<Acc, Epi, T::BM, T::BN>), dim3(pl.nsplit, ry), dim3(256), 0, s, ws,
                        pl.S, g.M, g.N, pl.split_tiles, epi);
+  }
   return hipGetLastError();
 }
 
