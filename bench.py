@@ -68,8 +68,9 @@ BATCH_ITERS = 100
 def run_batch(args, dev, steps, warmup):
     """64 uneven problems (square n in 128..1024, own PSF, rank 1..8, own
     lambda) in plain FP32: per step, the Kronecker approximation of every
-    PSF (one kron_approx_batch call), the batch setup (power iteration for every L, tile autotuning with
-    a cache file) and 100 iterations replayed from a HIP graph."""
+    PSF (one kron_approx_batch call), the batch setup (12 Lanczos steps for
+    every L, tile autotuning with a cache file) and 100 iterations replayed
+    from a HIP graph."""
     import tempfile
 
     import numpy as np
@@ -90,7 +91,7 @@ def run_batch(args, dev, steps, warmup):
     def step():
         kron = sfista.kron_approx_many(psf, [p.center for p in probs], [p.bc for p in probs], [p.r for p in probs])
         items = [(Bo, A, B, p.lam, None) for p, Bo, (A, B, _, _) in zip(probs, bobs, kron)]
-        b = sfista.Batch(items, precision="fp32", pair_state=False, max_iters=BATCH_ITERS, power_iters=30,
+        b = sfista.Batch(items, precision="fp32", pair_state=False, max_iters=BATCH_ITERS, l_estimate="lanczos",
                          autotune=True, graph=True)
         _, reps = b.solve(BATCH_ITERS, want_x=False)
         tiles = b.tiles()

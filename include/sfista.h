@@ -93,8 +93,9 @@ typedef struct {
     const double* v0;    /* (device) m x n start of the estimate of L, or NULL for a
                             fixed internal start */
     int l_estimate;      /* sfista_l_estimate: how L is estimated when L <= 0 (the
-                            single-image GEMM and FFT forms; the batched and
-                            differentiable forms take SFISTA_L_POWER only) */
+                            single-image GEMM and FFT forms and the batched form;
+                            the differentiable form takes no params and uses
+                            the power iteration) */
 } sfista_params;
 
 typedef struct {

@@ -611,7 +611,8 @@ struct sfista_batch {
   int choice[4] = {0, 0, 0, 0};     // 0 = the mode's big tile, 1 = TileS, 2 = Tile128
   void* dpow[2] = {};               // power iteration: F2 without Bobs, G2 storing A_s^T A_s V (per problem)
   std::vector<char> need_L;         // problems whose L the batch estimates
-  int power_steps = 30;
+  int power_steps = 30;             // steps of the estimate of L
+  int lanczos = 0;                  // 1: Lanczos estimate, 0: power iteration
   double* beta = nullptr;           // beta[k] = (t_k - 1) / t_{k+1}, beta[0] = 0
   int* counter = nullptr;           // iterations completed (device)
   hipGraphExec_t gexec = nullptr;
@@ -865,6 +866,133 @@ hipError_t batch_power(sfista_batch* b, const std::vector<const double*>& v0, in
   return hipSuccess;
 }
 
+// ---- batched Lanczos: the recurrence of run_lanczos for every problem at
+// once (same partial/sum structure per problem as a lone plan).
+struct LanczosImg {
+  const double* v0;   // start vector
+  double* w;          // the plan's aux: A_s^T A_s q_j, then the orthogonalised residual
+  double* q[2];       // q_j and q_{j-1} (ping-pong by step parity)
+  double* red;        // the plan's reduction partials [RED_BLOCKS] + scalars
+  double* coef;       // 2 x steps: alpha_j, beta_j^2
+  void* Y[2];         // F1 operand planes
+  long ldY;
+  int m, n;
+};
+
+// which: 0 = ||v0||^2, 1 = <q_cur, w>, 2 = the three-term update of w and ||w||^2
+static __global__ __launch_bounds__(RED_THREADS) void lz_partial_kernel(const LanczosImg* im, int which, int cur,
+                                                                        int j) {
+  __shared__ double sh[RED_THREADS / 64];
+  const LanczosImg& d = im[blockIdx.y];
+  const long total = (long)d.m * d.n;
+  const double* q = d.q[cur];
+  const double* qo = d.q[cur ^ 1];
+  double a = 0.0, b = 0.0;
+  if (which == 2) {
+    a = d.coef[2 * j];
+    b = j > 0 ? sqrt(d.coef[2 * j - 1]) : 0.0;
+  }
+  double acc = 0.0;
+  for (long e = blockIdx.x * (long)RED_THREADS + threadIdx.x; e < total; e += (long)RED_BLOCKS * RED_THREADS) {
+    if (which == 0) {
+      const double v = d.v0[e];
+      acc += v * v;
+    } else if (which == 1) {
+      acc += q[e] * d.w[e];
+    } else {
+      double v = d.w[e] - a * q[e];
+      if (j > 0) v -= b * qo[e];
+      d.w[e] = v;
+      acc += v * v;
+    }
+  }
+  const double t = block_sum(acc, sh);
+  if (threadIdx.x == 0) d.red[blockIdx.x] = t;
+}
+
+// Adds the partials in index order into the scalar slot (slot < 0) or coef[slot].
+static __global__ __launch_bounds__(RED_THREADS) void lz_finish_kernel(const LanczosImg* im, int slot) {
+  __shared__ double sh[RED_THREADS / 64];
+  const LanczosImg& d = im[blockIdx.y];
+  double acc = 0.0;
+  for (int e = threadIdx.x; e < RED_BLOCKS; e += RED_THREADS) acc += d.red[e];
+  const double t = block_sum(acc, sh);
+  if (threadIdx.x == 0) {
+    if (slot < 0) d.red[RED_BLOCKS] = t;
+    else d.coef[slot] = t;
+  }
+}
+
+// q_dst = src / sqrt(ss) (0 when ss is 0) and the F1 planes of it; src is
+// v0 with ss = ||v0||^2 for the start (j < 0), else w with ss = beta_j^2.
+template <int MODE>
+__global__ void lz_next_kernel(const LanczosImg* im, int dst, int j) {
+  const LanczosImg& d = im[blockIdx.y];
+  const double* src = j < 0 ? d.v0 : d.w;
+  const double ss = j < 0 ? d.red[RED_BLOCKS] : d.coef[2 * j + 1];
+  const double scale = ss > 0.0 ? 1.0 / sqrt(ss) : 0.0;
+  double* q = d.q[dst];
+  void* p[2] = {d.Y[0], d.Y[1]};
+  const int n = d.n;
+  const long total = (long)d.m * n;
+  for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < total; e += (long)gridDim.x * blockDim.x) {
+    const double v = src[e] * scale;
+    q[e] = v;
+    const long i = e / n, c = e - i * n;
+    store_planes<MODE>(p, op_index<MODE>(i, c, d.ldY), v);
+  }
+}
+
+// Estimates L for every problem by `steps` Lanczos steps from each plan's
+// start vector into Lout (host, count entries).
+template <int MODE>
+hipError_t batch_lanczos(sfista_batch* b, const std::vector<const double*>& v0, int steps,
+                         std::vector<double>& Lout) {
+  const int cnt = b->count;
+  std::vector<LanczosImg> im(cnt);
+  double* coef = static_cast<double*>(b->arena.alloc_zero(sizeof(double) * 2 * steps * cnt, b->s));
+  if (!coef) return hipErrorOutOfMemory;
+  for (int i = 0; i < cnt; ++i) {
+    sfista_plan* h = b->plans[i];
+    const size_t bytes = (size_t)h->m * h->n * 8;
+    for (int k = 0; k < 2; ++k)
+      if (!h->lzq[k] && !(h->lzq[k] = static_cast<double*>(h->mem->alloc_zero(bytes, b->s))))
+        return hipErrorOutOfMemory;
+    im[i] = LanczosImg{v0[i], h->aux, {h->lzq[0], h->lzq[1]}, h->red, coef + (size_t)2 * steps * i,
+                       {h->Y[0], h->Y[1]}, h->ldY, h->m, h->n};
+  }
+  LanczosImg* dim = static_cast<LanczosImg*>(b->arena.alloc_zero(sizeof(LanczosImg) * cnt, b->s));
+  if (!dim) return hipErrorOutOfMemory;
+  hipError_t e = hipMemcpyAsync(dim, im.data(), sizeof(LanczosImg) * cnt, hipMemcpyHostToDevice, b->s);
+  if (e != hipSuccess) return e;
+  const dim3 rg(RED_BLOCKS, cnt), fg(1, cnt), pg(std::max(1, EW_BLOCKS / cnt), cnt);
+  hipLaunchKernelGGL(lz_partial_kernel, rg, dim3(RED_THREADS), 0, b->s, dim, 0, 0, 0);
+  hipLaunchKernelGGL(lz_finish_kernel, fg, dim3(RED_THREADS), 0, b->s, dim, -1);
+  hipLaunchKernelGGL(lz_next_kernel<MODE>, pg, dim3(EW_THREADS), 0, b->s, dim, 0, -1);
+  int cur = 0;
+  for (int j = 0; j < steps; ++j) {
+    if ((e = launch_product<MODE, EpiStack<MODE>>(b, 0)) != hipSuccess) return e;
+    if ((e = launch_product<MODE, EpiResid<MODE>>(b, 1, b->dpow[0])) != hipSuccess) return e;
+    if ((e = launch_product<MODE, EpiStack<MODE>>(b, 2)) != hipSuccess) return e;
+    if ((e = launch_product<MODE, EpiStore<MODE>>(b, 3, b->dpow[1])) != hipSuccess) return e;
+    hipLaunchKernelGGL(lz_partial_kernel, rg, dim3(RED_THREADS), 0, b->s, dim, 1, cur, j);
+    hipLaunchKernelGGL(lz_finish_kernel, fg, dim3(RED_THREADS), 0, b->s, dim, 2 * j);
+    hipLaunchKernelGGL(lz_partial_kernel, rg, dim3(RED_THREADS), 0, b->s, dim, 2, cur, j);
+    hipLaunchKernelGGL(lz_finish_kernel, fg, dim3(RED_THREADS), 0, b->s, dim, 2 * j + 1);
+    if (j + 1 < steps) {
+      hipLaunchKernelGGL(lz_next_kernel<MODE>, pg, dim3(EW_THREADS), 0, b->s, dim, cur ^ 1, j);
+      cur ^= 1;
+    }
+  }
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  std::vector<double> hc((size_t)2 * steps * cnt);
+  if ((e = hipMemcpyAsync(hc.data(), coef, hc.size() * 8, hipMemcpyDeviceToHost, b->s)) != hipSuccess) return e;
+  if ((e = hipStreamSynchronize(b->s)) != hipSuccess) return e;
+  Lout.resize(cnt);
+  for (int i = 0; i < cnt; ++i) Lout[i] = lanczos_ritz_max(hc.data() + (size_t)2 * steps * i, steps);
+  return hipSuccess;
+}
+
 // Times the tile shapes of every product on the batch itself and keeps the
 // fastest; the state is reset afterwards.
 template <int MODE>
@@ -957,8 +1085,9 @@ int batch_estimate_L(sfista_batch* b) {
     v0[i] = h->v0buf;
   }
   std::vector<double> L;
-  hipError_t e = batch_power<MODE>(b, v0, b->power_steps, L);
-  if (e != hipSuccess) return hip_fail(e, "batch power iteration");
+  hipError_t e = b->lanczos ? batch_lanczos<MODE>(b, v0, b->power_steps, L)
+                             : batch_power<MODE>(b, v0, b->power_steps, L);
+  if (e != hipSuccess) return hip_fail(e, b->lanczos ? "batch Lanczos estimate of L" : "batch power iteration");
   for (int i = 0; i < cnt; ++i) {
     if (!b->need_L[i]) continue;
     if (!isfinite(L[i]) || !(L[i] > 0.0)) return set_error(SFISTA_ERR_NONFINITE, "problem %d: Lipschitz estimate is %g", i, L[i]);
@@ -1046,8 +1175,6 @@ int sfista_batch_setup(const sfista_batch_item* items, int count, const sfista_p
     return set_error(SFISTA_ERR_UNSUPPORTED, "unknown precision %d", common->precision);
   if (common->x0 || common->v0)
     return set_error(SFISTA_ERR_UNSUPPORTED, "batch problems start from X_0 = 0 and an internal power start");
-  if (common->l_estimate == SFISTA_L_LANCZOS)
-    return set_error(SFISTA_ERR_UNSUPPORTED, "the batch estimates L by power iteration only");
   for (int i = 0; i < count; ++i) {
     sfista_params p = *common;
     p.lambda = items[i].lambda;
@@ -1067,7 +1194,8 @@ int sfista_batch_setup(const sfista_batch_item* items, int count, const sfista_p
     delete b;
     return hip_fail(e, "batch stream");
   }
-  b->power_steps = common->power_iters > 0 ? common->power_iters : 30;
+  b->lanczos = common->l_estimate == SFISTA_L_LANCZOS ? 1 : 0;
+  b->power_steps = common->power_iters > 0 ? common->power_iters : (b->lanczos ? 12 : 30);
   for (int i = 0; i < count; ++i) {
     sfista_params p = *common;
     p.lambda = items[i].lambda;

@@ -373,13 +373,14 @@ class Batch:
     """Many independent sFISTA problems advanced together (Algorithm 2 on
     each): every GEMM phase of one iteration is a single grouped launch over
     all problems.  ``problems`` is a sequence of ``(Bobs, A, B, lam, L)`` with
-    device float64 tensors; ``L = None`` estimates it by ``power_iters`` power
-    steps.  ``autotune`` times the tile shapes of each phase on the batch itself;
-    ``graph`` replays the iterations from a captured HIP graph."""
+    device float64 tensors; ``L = None`` estimates it (``l_estimate``, with
+    ``power_iters`` steps) for all such problems at once.  ``autotune`` times
+    the tile shapes of each phase on the batch itself; ``graph`` replays the
+    iterations from a captured HIP graph."""
 
     def __init__(self, problems, precision: str = "bf16x3", max_iters: int = 1000, nonneg: bool = False,
                  power_iters: int = 0, pair_state: bool = True, autotune: bool = False, graph: bool = False,
-                 stream=None):
+                 stream=None, l_estimate: str = "power"):
         items = (BatchItem * max(len(problems), 1))()
         self.shapes = []
         self.device = None
@@ -393,7 +394,7 @@ class Batch:
             self.shapes.append((m, n))
             self.device = Bobs.device
         common = Params(0.0, 0.0, PRECISIONS[precision], int(bool(nonneg)), int(power_iters),
-                        int(bool(pair_state)), None, None)
+                        int(bool(pair_state)), None, None, _l_estimate(l_estimate))
         flags = (BATCH_AUTOTUNE if autotune else 0) | (BATCH_GRAPH if graph else 0)
         h = ctypes.c_void_p()
         self._h = None

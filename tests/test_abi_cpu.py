@@ -140,7 +140,6 @@ def _items(count=2, **kw):
     (2, 10, {}, dict(precision=9), -2),
     (2, 10, {}, dict(x0=0x2000), -2),             # batch problems start from zero
     (2, 10, {}, dict(power_iters=-2), -1),
-    (2, 10, {}, dict(l_estimate=1), -2),          # the batch estimates L by power iteration only
     (2, 10, {}, dict(l_estimate=3), -1),
 ])
 def test_batch_setup_rejects_invalid_arguments(L, count, max_iters, item, common, expect):

@@ -213,25 +213,26 @@ def test_single_problem_batch(sf, case):
     b.close()
 
 
+@pytest.mark.parametrize("est,steps", [("power", 25), ("lanczos", 12)])
 @pytest.mark.parametrize("mode,tol", [("fp64", 1e-12), ("fp32", 1e-6)])
-def test_batched_power_iteration_matches_lone_plans(sf, case, mode, tol):
-    """Problems given without L: the batch estimates every L in one batched
-    power iteration (grouped products, per-problem norms), from the same
-    internal start vector and with the same reduction structure as a lone
-    plan.  Each estimate equals the lone plan's up to the rounding of the
-    products' different K order; the lone plan's estimate is itself held to
-    the oracle's power iteration in test_gpu_parity.  The iterates that
-    follow match the lone plans' to the mode's tolerance."""
+def test_batched_estimate_of_L_matches_lone_plans(sf, case, mode, tol, est, steps):
+    """Problems given without L: the batch estimates every L at once (power
+    iteration or Lanczos; grouped products, per-problem reductions), from
+    the same internal start vector and with the same reduction structure as
+    a lone plan.  Each estimate equals the lone plan's up to the rounding of
+    the products' different K order; the lone plan's estimates are held to
+    the oracle's in test_gpu_parity.  The iterates that follow match the
+    lone plans' to the mode's tolerance."""
     probs = [(dev(p.bobs), dev(K), dev(H), p.lam, None) for p, K, H, L, _ in case]
-    b = sf.Batch(probs, precision=mode, max_iters=ITERS, power_iters=25)
+    b = sf.Batch(probs, precision=mode, max_iters=ITERS, power_iters=steps, l_estimate=est)
     Xb, reps = b.solve(ITERS)
     b.close()
     for (p, K, H, L, _), rp, xb in zip(case, reps, Xb):
-        s = sf.Solver(dev(p.bobs), dev(K), dev(H), lam=p.lam, precision=mode, power_iters=25)
+        s = sf.Solver(dev(p.bobs), dev(K), dev(H), lam=p.lam, precision=mode, power_iters=steps, l_estimate=est)
         Ls = s.L
         X, _ = s.solve(ITERS)
         s.close()
-        say(f"[batch power {mode}] {p.name}: batch L {rp['L']:.15g} lone {Ls:.15g}")
+        say(f"[batch {est} {mode}] {p.name}: batch L {rp['L']:.15g} lone {Ls:.15g}")
         assert math.isclose(rp["L"], Ls, rel_tol=tol)
         assert rel(host(xb), host(X)) < (1e-10 if mode == "fp64" else 1e-4)
 
