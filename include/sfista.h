@@ -140,7 +140,7 @@ int kron_approx(const double* P, int m, int n, int l, int q, int bc, int r,
  *   eps_s  (host, out, nullable) count entries.
  * Every image is checked as kron_approx checks it before any work is queued
  * (the message names the image).  Each image's kernels are those of
- * kron_approx, queued on one of up to four internal streams of default
+ * kron_approx, queued on one of up to sixteen internal streams of default
  * priority so that several images run at once; they start after the work
  * already queued on `stream`, and the call synchronises `stream` before
  * returning.  Results equal kron_approx's bit for bit. */
