@@ -238,13 +238,15 @@ def test_batched_estimate_of_L_matches_lone_plans(sf, case, mode, tol, est, step
 
 
 def test_kron_approx_many_equals_single_calls(sf):
-    """The batched Kronecker setup of nine PSFs (more images than internal
-    streams; both boundaries, ragged sizes, ranks 1..6) equals kron_approx
-    called image by image, bit for bit: factors, sigma and eps_s."""
+    """The batched Kronecker setup of twenty PSFs (more images than the
+    sixteen internal streams, so streams are reused; both boundaries, ragged
+    sizes, ranks 1..6) equals kron_approx called image by image, bit for
+    bit: factors, sigma and eps_s."""
     import torch
     shapes = [(33, 47, 2, O.BC_ZERO), (64, 48, 3, O.BC_REFLEXIVE), (128, 128, 5, O.BC_REFLEXIVE),
               (200, 136, 1, O.BC_ZERO), (257, 130, 4, O.BC_REFLEXIVE), (40, 40, 6, O.BC_ZERO),
               (96, 160, 2, O.BC_REFLEXIVE), (17, 9, 3, O.BC_ZERO), (300, 300, 5, O.BC_REFLEXIVE)]
+    shapes += [(24 + 7 * t, 30 + 5 * t, 1 + t % 4, t % 2) for t in range(11)]
     Ps, centers, bcs, rs = [], [], [], []
     for t, (m, n, r, bc) in enumerate(shapes):
         c = (m // 2 - t % 3, n // 2 + t % 2)
