@@ -228,6 +228,62 @@ __global__ __launch_bounds__(KT) void mat_cols_kernel(const double* X, int rows,
   }
 }
 
+// The same product for p <= PC, RB rows per block: each V element loaded
+// serves RB rows (the one-row kernel re-reads all of V from L2 per row).
+// Every output keeps the one-row kernel's order of summation.
+template <int PC, int RB>
+__global__ __launch_bounds__(KT) void mat_cols_rows_kernel(const double* X, int rows, int cols, const double* V,
+                                                           int p, double* out) {
+  __shared__ double sh[RB * PC * 4];
+  const int a0 = blockIdx.x * RB;
+  double acc[RB][PC];
+#pragma unroll
+  for (int t = 0; t < RB; ++t)
+#pragma unroll
+    for (int c = 0; c < PC; ++c) acc[t][c] = 0.0;
+  for (int b = threadIdx.x; b < cols; b += KT) {
+    double v[PC];
+#pragma unroll
+    for (int c = 0; c < PC; ++c) v[c] = c < p ? V[(long)c * cols + b] : 0.0;
+#pragma unroll
+    for (int t = 0; t < RB; ++t) {
+      if (a0 + t < rows) {
+        const double x = X[(long)(a0 + t) * cols + b];
+#pragma unroll
+        for (int c = 0; c < PC; ++c) acc[t][c] += x * v[c];
+      }
+    }
+  }
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+  for (int t = 0; t < RB; ++t)
+#pragma unroll
+    for (int c = 0; c < PC; ++c) {
+      double w = acc[t][c];
+      for (int o = 32; o > 0; o >>= 1) w += __shfl_down(w, o, 64);
+      if (lane == 0) sh[(t * PC + c) * 4 + wave] = w;
+    }
+  __syncthreads();
+  for (int i = threadIdx.x; i < RB * p; i += KT) {
+    const int t = i / p, c = i - t * p;
+    if (a0 + t < rows) {
+      const double* q = sh + (t * PC + c) * 4;
+      out[(long)c * rows + a0 + t] = ((q[0] + q[1]) + q[2]) + q[3];
+    }
+  }
+}
+
+// out = X V^T through the multi-row kernel when p allows it.
+void mat_cols(const double* X, int rows, int cols, const double* V, int p, double* out, hipStream_t s) {
+  if (p <= 16) {
+    constexpr int RB = 4;
+    hipLaunchKernelGGL((mat_cols_rows_kernel<16, RB>), dim3((rows + RB - 1) / RB), dim3(KT), 0, s, X, rows, cols, V,
+                       p, out);
+  } else {
+    hipLaunchKernelGGL(mat_cols_kernel, dim3(rows), dim3(KT), 0, s, X, rows, cols, V, p, out);
+  }
+}
+
 // Modified Gram-Schmidt, applied twice, on p columns of length d (single
 // block).  A column whose residual after projection falls below 1e-10 of its
 // norm before projection is numerically dependent on the previous ones (the
@@ -582,9 +638,9 @@ int kron_enqueue(const double* P, int m, int n, int l, int q, int bc, int r, dou
   // randomized subspace iteration: Z <- orth(P_bar^T orth(P_bar Z))
   hipLaunchKernelGGL(hash_fill_kernel, ew, et, 0, s, Zc, (long)p * n, 0x51f15eedull);
   for (int it = 0; it < SUBSPACE_ITERS; ++it) {
-    hipLaunchKernelGGL(mat_cols_kernel, dim3(m), dim3(KT), 0, s, Pb, m, n, Zc, p, Yc);
+    mat_cols(Pb, m, n, Zc, p, Yc, s);
     orthonormalise(Yc, p, m, s);
-    hipLaunchKernelGGL(mat_cols_kernel, dim3(n), dim3(KT), 0, s, Pt, n, m, Yc, p, Zc);
+    mat_cols(Pt, n, m, Yc, p, Zc, s);
     if (it + 1 < SUBSPACE_ITERS) orthonormalise(Zc, p, n, s);
   }
   // Z = P_bar^T Y with Y orthonormal: P_bar ~ Y Z^T; SVD of Z by one-sided Jacobi
