@@ -231,8 +231,10 @@ typedef struct sfista_batch* sfista_batch_handle;
 #define SFISTA_BATCH_GRAPH 2     /* replay chunks of 10 iterations from a captured HIP graph */
 
 /* Build a batch of `count` problems.  `common` (host) supplies precision,
- * nonneg, power_iters and pair_state for all of them (its lambda, L, x0, v0
- * are ignored; every problem starts from X_0 = 0).  `max_iters` bounds the
+ * nonneg, power_iters, l_estimate and pair_state for all of them (its lambda
+ * and L are ignored; x0 and v0 must be NULL: every problem starts from
+ * X_0 = 0 and estimates L, when its item's L <= 0, from a lone plan's
+ * internal start, all such problems together).  `max_iters` bounds the
  * iterations the batch may run (the size of its momentum table).  `flags`
  * is a mask of SFISTA_BATCH_*.  With SFISTA_BATCH_AUTOTUNE the choice of tile
  * shape per product is cached in the file named by the environment variable
