@@ -143,16 +143,16 @@ def test_power_iteration_matches_oracle(sf):
     s.close()
 
 
-@pytest.mark.parametrize("steps", [12, 30])
+@pytest.mark.parametrize("steps", [0, 12, 30])
 def test_lanczos_estimate_matches_oracle(sf, steps):
     """Section 4's Lanczos estimate of L with the transform passes against
-    the oracle's Lanczos from the same start."""
+    the oracle's Lanczos from the same start (steps = 0: the default 12)."""
     p = S.config(2, n=192)
     l, q = p.center
     K, H, _, _, oh, ok = O.kron_approx64(p.psf, l, q, p.bc, p.r)
     s = sf.FftSolver(dev(p.bobs), dev(oh), dev(ok), l, q, p.bc, lam=p.lam, power_iters=steps, v0=dev(p.v0),
                      l_estimate="lanczos")
-    Lo = O.lipschitz_lanczos(K, H, p.v0, steps)
+    Lo = O.lipschitz_lanczos(K, H, p.v0, steps or 12)
     say(f"[fft lanczos {steps}] gpu={s.L:.12e} oracle={Lo:.12e} rel={abs(s.L - Lo) / Lo:.2e}")
     assert math.isclose(s.L, Lo, rel_tol=1e-5)
     s.close()
