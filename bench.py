@@ -443,8 +443,8 @@ def main():
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
-              "(the design for sharding is described in DESIGN.md).", file=sys.stderr)
+        print("bench.py measures one GPU only: the library has no multi-GPU path; run it with --gpus 1 "
+              "(the shard2048g8 workload times one GPU's share of a sharded image).", file=sys.stderr)
         sys.exit(2)
 
     # hardware queues of this process, read when HIP starts: the batched
