@@ -178,7 +178,7 @@ def _problem(name, m, n, psf, bc, r, lam, iters, nl, c, precision, seed_shift=0)
     return Problem(name, x, psf, center, bc, r, lam, iters, nl, b, bobs, v0, precision)
 
 
-CONFIGS = {
+WORKLOADS = {   # the named single-image workloads, by number
     1: dict(name="fp64-64", n=64, sigma=(2.0, 4.0), theta=30.0, bc=BC_ZERO, r=3,
             nl=0.01, lam=0.02, iters=100, precision="fp64"),
     2: dict(name="fp32-512", n=512, sigma=(3.0, 8.0), theta=45.0, bc=BC_REFLEXIVE, r=5,
@@ -189,10 +189,11 @@ CONFIGS = {
 
 
 def config(c: int, n: Optional[int] = None, iters: Optional[int] = None) -> Problem:
-    """Problem for configuration ``c`` (1: FP64 64^2, 2: FP32 512^2,
-    3: precision study 2048^2).  ``n`` overrides the image size (same
-    generator recipe, used for reduced-size test cases)."""
-    cfg = CONFIGS[c]
+    """Problem of workload ``c``: 1 is the FP64 64^2 case (zero boundary,
+    r = 3), 2 the FP32 512^2 case (reflexive, r = 5), 3 the BF16X3 2048^2
+    precision study (reflexive, r = 5, 300 iterations).  ``n`` overrides the
+    image size (same generator recipe, used for reduced-size test cases)."""
+    cfg = WORKLOADS[c]
     size = cfg["n"] if n is None else n
     psf = gaussian_psf(size, size, cfg["sigma"], cfg["theta"])
     return _problem(cfg["name"], size, size, psf, cfg["bc"], cfg["r"], cfg["lam"],

@@ -259,7 +259,7 @@ def test_bf16x3_target_config3_recipe_512(sf):
     """The 2048^2 precision configuration's recipe (reflexive, sigma = (4, 12),
     theta = 30, r = 5, 1% noise, lambda = 0.02, 300 iterations) at 512^2:
     BF16X3 with float-float state within 1e-5 of the FP64 oracle."""
-    cfg = S.CONFIGS[3]
+    cfg = S.WORKLOADS[3]
     n = 512
     psf = S.gaussian_psf(n, n, cfg["sigma"], cfg["theta"])
     x = S.make_image(n, n, S.SEED_IMAGE + 3)
