@@ -1122,14 +1122,19 @@ int batch_setup_mode(sfista_batch* b) {
     b->choice[q] = b->nwork[q][0] >= 2 * slots ? 0 : (shape_offered<MODE>(2) && b->nwork[q][2] >= 2 * cus) ? 2 : 1;
   for (int q = 0; q < 4; ++q)
     if (!shape_offered<MODE>(b->choice[q])) b->choice[q] = 1;
+  // a cached choice applies at once, so that the estimate of L already runs
+  // on the tuned shapes (shapes do not change results); otherwise the timing
+  // waits for L, which the update epilogue of G2 needs
+  const bool tune = (b->flags & SFISTA_BATCH_AUTOTUNE) != 0;
+  const std::string key = tune ? batch_key(b) : std::string();
+  const bool cached = tune && tune_cache_lookup(key, b->choice);
+  for (int q = 0; q < 4; ++q)
+    if (!shape_offered<MODE>(b->choice[q])) b->choice[q] = 1;   // a cache line from elsewhere
   if ((rc = batch_estimate_L<MODE>(b)) != SFISTA_OK) return rc;
-  if (b->flags & SFISTA_BATCH_AUTOTUNE) {
-    const std::string key = batch_key(b);
-    if (!tune_cache_lookup(key, b->choice)) {
-      hipError_t e = batch_autotune<MODE>(b);
-      if (e != hipSuccess) return hip_fail(e, "batch autotune");
-      tune_cache_store(key, b->choice);
-    }
+  if (tune && !cached) {
+    hipError_t e = batch_autotune<MODE>(b);
+    if (e != hipSuccess) return hip_fail(e, "batch autotune");
+    tune_cache_store(key, b->choice);
   }
   hipError_t e = hipStreamSynchronize(b->s);
   if (e != hipSuccess) return hip_fail(e, "batch setup");
