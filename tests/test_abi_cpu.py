@@ -229,3 +229,14 @@ def test_fft_calls_reject_null(L):
     L.sfista_fft_destroy(None)
     assert L.kron_generators(FAKE, 4, 4, 1, 1, 0, 1, None, FAKE, None, None, None) == -1
     assert L.kron_generators(FAKE, 4, 4, 4, 1, 0, 1, FAKE, FAKE, None, None, None) == -1
+
+
+def test_kron_approx_many_checks_lengths_before_the_library():
+    """The Python entry of the batched setup: an empty list needs no work, and
+    per-PSF arguments of the wrong length are refused before any call."""
+    from paper_1901_00913_amd import sfista
+    assert sfista.kron_approx_many([], [], 1, 1) == []
+    with pytest.raises(ValueError):
+        sfista.kron_approx_many([object(), object()], [(1, 1)], 1, 2)
+    with pytest.raises(ValueError):
+        sfista.kron_approx_many([object()], [(1, 1)], [0, 1], 2)
