@@ -371,8 +371,16 @@ struct EpiResid {
       if (cnt == 8 && (i & 7) == 0 && !copy && !g[0]) {
         float r[8];
         const float z[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+        if (bobs_t && (m & 3) == 0) {   // rows start 16-byte aligned: two vector loads
+          const float4* b4 = reinterpret_cast<const float4*>(bobs_t + (long)j * m + i);
+          const float4 b0 = b4[0], b1 = b4[1];
+          const float bb[8] = {b0.x, b0.y, b0.z, b0.w, b1.x, b1.y, b1.z, b1.w};
 #pragma unroll
-        for (int q = 0; q < 8; ++q) r[q] = bobs_t ? v[q] - bobs_t[(long)j * m + i + q] : v[q];
+          for (int q = 0; q < 8; ++q) r[q] = v[q] - bb[q];
+        } else {
+#pragma unroll
+          for (int q = 0; q < 8; ++q) r[q] = bobs_t ? v[q] - bobs_t[(long)j * m + i + q] : v[q];
+        }
         store8_planes<MODE>(out, op_index<MODE>(j, i, ldo), r, z);
         return;
       }
